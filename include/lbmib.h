@@ -1,0 +1,205 @@
+/*
+ * lbmib — MI355X (gfx950) lattice Boltzmann + immersed boundary + finite
+ * element bead-spring microswimmer step.
+ *
+ * Method: Geyer et al., "Lattice Boltzmann Simulations of Two Linear
+ * Microswimmers Using the Immersed Boundary Method" (arXiv 2202.12147),
+ * Sec. 2.1 (D3Q19 BGK fluid, Eqs. lbe, lbm:equilibrium, sc), Sec. 2.2
+ * (three-bead spring swimmer, driving and spring forces, Skalak / Helfrich /
+ * volume membrane energies of icosphere beads), Sec. 2.3 (IBM spreading and
+ * interpolation with a discrete delta kernel, Eqs. spreading and
+ * interpolation).
+ *
+ * Conventions shared by every call:
+ *   - Return value 0 on success, a negative LBM_E* code on error.  No C++
+ *     exception crosses this boundary.  lbm_last_error() gives the message of
+ *     the handle's most recent error.
+ *   - Lattice units: node (i,j,k) sits at integer coordinates; lengths in
+ *     lattice spacings, times in steps, rho0 = 1 (Sec. 2.1).
+ *   - Lattice fields are laid out [component][z][y][x], x fastest.
+ *   - Populations: D3Q19 with index 0 = rest, 1..6 = +x,-x,+y,-y,+z,-z,
+ *     7..18 = (+1,+1,0),(-1,-1,0),(+1,-1,0),(-1,+1,0),(+1,0,+1),(-1,0,-1),
+ *     (+1,0,-1),(-1,0,+1),(0,+1,+1),(0,-1,-1),(0,+1,-1),(0,-1,+1).  They
+ *     cross the boundary as deviations g_i = f_i - w_i from the rest state
+ *     (w_i the lattice weights of Sec. 2.1), in float64.
+ *   - Marker (mesh node) arrays are [marker][xyz] in float64, unwrapped (they
+ *     may leave the box; grid indices wrap periodically).
+ *   - Pointers marked "device" must be device memory of the handle's device;
+ *     "host" pointers are ordinary host memory.  The caller owns every buffer
+ *     it passes; the handle owns its internal device memory and frees it in
+ *     lbm_destroy.
+ *   - All work is enqueued on the handle's stream.  Calls that return data to
+ *     the host (or into caller device memory) synchronise that stream before
+ *     returning.  One handle must not be used from two host threads at once.
+ */
+#ifndef LBMIB_H
+#define LBMIB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ---------------------------------------------------------- */
+#define LBM_OK 0
+#define LBM_EINVAL -1      /* invalid argument (bad size, enum, tau <= 1/2 ...) */
+#define LBM_ENOMEM -2      /* device or host allocation failed */
+#define LBM_EDEVICE -3     /* a HIP runtime call failed */
+#define LBM_ESTATE -4      /* call not allowed in the current state */
+#define LBM_ENONFINITE -5  /* NaN or Inf found in the conserved sums */
+#define LBM_EIO -6         /* file could not be read or written */
+#define LBM_EOVERFLOW -7   /* a bead outgrew the region reserved for it */
+
+/* ---- enums ---------------------------------------------------------------- */
+/* Body-force scheme.  SHAN_CHEN shifts the equilibrium velocity,
+ * rho u_eq = sum f c + tau F (Sec. 2.1, Eq. sc), as the paper does.  GUO
+ * uses u = (sum f c + F/2)/rho in the equilibrium plus the source term
+ * (1 - 1/(2 tau)) w_i [3 (c_i - u) + 9 (c_i . u) c_i] . F.  In both the
+ * physical velocity is rho u = sum f c + F/2 (Sec. 2.1). */
+typedef enum { LBM_GUO = 0, LBM_SHAN_CHEN = 1 } lbm_forcing;
+
+/* Population storage on the device.  Both store the deviation g = f - w from
+ * the rest state and compute in FP32; FP16_SHIFTED stores g * scale rounded
+ * to nearest-even half precision. */
+typedef enum { LBM_FP32_SHIFTED = 0, LBM_FP16_SHIFTED = 1 } lbm_storage;
+
+/* ---- descriptors ---------------------------------------------------------- */
+typedef struct {
+  int32_t nx, ny, nz; /* fully periodic box (Sec. 3) */
+} lbm_grid;
+
+typedef struct {
+  int32_t storage;     /* lbm_storage */
+  int32_t delta_width; /* IBM kernel support in nodes: 2 (two-point linear, Sec.
+                          2.3), 3 (Roma-Peskin-Berger) or 4 (Peskin) */
+  float fp16_scale;    /* power of two S for FP16_SHIFTED (0 = default 1) */
+  int32_t use_graphs;  /* 1 = replay steps from captured HIP graphs */
+  void* stream;        /* hipStream_t to enqueue on; NULL = own stream */
+} lbm_opts;
+
+typedef struct {
+  double centre[3]; /* initial bead centre */
+  double radius;    /* shell radius */
+  int32_t level;    /* icosphere refinement level: 20*4^level triangles */
+  double kappa_s;   /* Skalak shear modulus (Sec. 2.2) */
+  double C;         /* Skalak area constant, kappa_a/kappa_s = 1 + 2C */
+  double kappa_b;   /* Helfrich bending modulus (Kantor-Nelson discretised) */
+  double kappa_v;   /* volume penalty modulus, Eq. (vol_cons) */
+} lbm_bead_desc;
+
+typedef struct {
+  double k;  /* harmonic spring constant (Sec. 2.2) */
+  double L0; /* equilibrium length L_spring */
+} lbm_spring_desc;
+
+typedef struct {
+  double A;      /* amplitude on bead 1: f1 = A sin(w t + phi0) x (Sec. 2.2) */
+  double B;      /* amplitude on bead 3: f3 = B sin(w t + phi0 + alpha) x */
+  double period; /* T, w = 2 pi / T, t = step index */
+  double alpha;  /* phase shift between the outer beads */
+  double phi0;   /* common phase offset (0 in the paper) */
+} lbm_actuation_desc;
+
+typedef struct lbm_handle lbm_handle;
+
+/* ---- lifetime --------------------------------------------------------------- */
+/* Create a periodic D3Q19 BGK fluid at rest (rho = 1, u = 0), relaxation time
+ * tau (Eq. lbe; viscosity nu = (tau - 1/2)/3, Sec. 2.1).  Requires tau > 1/2,
+ * every grid edge >= 16, forcing and opts valid.  opts may be NULL (FP32,
+ * 3-point kernel, graphs on, own stream).  *out receives the handle.
+ * Errors: LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE. */
+int lbm_create(const lbm_grid* grid, double tau, int forcing, const lbm_opts* opts,
+               lbm_handle** out);
+
+/* Release all device memory and the handle.  Accepts NULL. */
+int lbm_destroy(lbm_handle* h);
+
+/* Add one three-bead swimmer (Sec. 2.2, Fig. 1): beads[0..2] in order along
+ * the swimmer, springs[0] joins beads 0-1, springs[1] joins beads 2-1, the
+ * driving forces act along x.  Each bead is an icosphere (an icosahedron
+ * refined `level` times, new vertices projected onto the sphere) whose
+ * initial shape is stress-free.  Allowed only before the first lbm_step
+ * (LBM_ESTATE afterwards).  *id (may be NULL) receives the swimmer index.
+ * Errors: LBM_EINVAL (radius <= 0, level outside 0..5, bead larger than a
+ * third of the box), LBM_ESTATE, LBM_ENOMEM, LBM_EDEVICE. */
+int lbm_swimmer_add(lbm_handle* h, const lbm_bead_desc beads[3],
+                    const lbm_spring_desc springs[2], const lbm_actuation_desc* act,
+                    int32_t* id);
+
+/* Uniform body force density added to F at every node (test and drag setups). */
+int lbm_set_body_force(lbm_handle* h, const double g[3]);
+
+/* ---- stepping ---------------------------------------------------------------- */
+/* Advance n time steps, asynchronously on the handle's stream.  One step:
+ * bead centres, driving + spring + membrane forces, spreading (Eq.
+ * spreading), fused stream-collide (Eq. lbe), interpolation (Eq.
+ * interpolation) and marker advection r += U.  Errors: LBM_EINVAL (n < 0),
+ * LBM_EDEVICE. */
+int lbm_step(lbm_handle* h, int64_t n);
+
+/* Block until all enqueued work is done; reports LBM_EOVERFLOW if a bead
+ * outgrew its reserved tile region during the steps. */
+int lbm_sync(lbm_handle* h);
+
+/* ---- observables (synchronous) ---------------------------------------------- */
+int64_t lbm_time(const lbm_handle* h);    /* steps taken */
+int32_t lbm_n_markers(const lbm_handle* h);
+int32_t lbm_n_swimmers(const lbm_handle* h);
+
+/* Swimmer centres x_cm = mean of the three bead centres (Eq. vel_swim), each
+ * bead centre the mean of its mesh nodes; host out[n_swimmers*3], float64. */
+int lbm_get_swimmer_centres(lbm_handle* h, double* out);
+/* Bead centres, host out[3*n_swimmers*3], float64. */
+int lbm_get_bead_centres(lbm_handle* h, double* out);
+/* Marker positions, host out[n_markers*3], float64 (unwrapped). */
+int lbm_get_markers(lbm_handle* h, double* out);
+/* Interpolated marker velocities of the last step, host out[n_markers*3]. */
+int lbm_get_marker_velocities(lbm_handle* h, double* out);
+/* Total nodal forces f_tot of the last step (Sec. 2.2), host out[n_markers*3]. */
+int lbm_get_marker_forces(lbm_handle* h, double* out);
+
+/* Physical fluid velocity u_n = (sum f c + F/2)/rho of the last completed
+ * step n (the velocity the markers were advected with), dst[3][nz][ny][nx]
+ * float32; on_device = 1: dst is device memory, 0: host memory.  Before the
+ * first step it is zero. */
+int lbm_get_velocity(lbm_handle* h, float* dst, int on_device);
+/* Density rho_n of the last completed step, dst[nz][ny][nx] float32. */
+int lbm_get_density(lbm_handle* h, float* dst, int on_device);
+
+/* out[0] = sum over nodes and populations of f*, out[1..3] = sum f* c, of the
+ * current post-collision state, reduced in float64 on the device.
+ * LBM_ENONFINITE if any sum is NaN or Inf. */
+int lbm_get_conserved(lbm_handle* h, double out[4]);
+
+/* Population deviations g = f* - w of the current post-collision state,
+ * host float64 [19][nz][ny][nx].  set: before the first step only. */
+int lbm_set_populations(lbm_handle* h, const double* dev);
+int lbm_get_populations(lbm_handle* h, double* dev);
+
+/* ---- checkpoint ---------------------------------------------------------------- */
+/* Write / restore the full dynamic state (populations, forces, tile stamps,
+ * markers, step counter) to / from a file.  Restoring needs a handle created
+ * with the same grid, options and swimmers; the restart is bit-exact.
+ * Errors: LBM_EIO, LBM_EINVAL (mismatched handle). */
+int lbm_save(lbm_handle* h, const char* path);
+int lbm_load(lbm_handle* h, const char* path);
+
+/* ---- measurement ------------------------------------------------------------ */
+/* When on, lbm_step runs without graphs and brackets every stream-collide
+ * launch with HIP events on the handle's stream; lbm_kernel_time returns the
+ * summed kernel time (ms) and launch count since timing was switched on. */
+int lbm_set_kernel_timing(lbm_handle* h, int on);
+int lbm_kernel_time(lbm_handle* h, double* ms, int64_t* launches);
+/* Algorithmic bytes one stream-collide launch moves (19 populations read and
+ * written once per node at the storage width). */
+int64_t lbm_bytes_per_step(const lbm_handle* h);
+
+/* ---- errors ---------------------------------------------------------------- */
+const char* lbm_strerror(int code);
+const char* lbm_last_error(const lbm_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

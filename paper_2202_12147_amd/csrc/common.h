@@ -1,0 +1,127 @@
+// Internal definitions shared by the lbmib HIP translation units.
+//
+// Device layout (one allocation per array, all boxes of a batch concatenated):
+//   populations  pop[parity][q][node]   q-plane stride `pstride` elements,
+//                                       256-byte aligned; FP32 or FP16
+//   force        F[3][node]             FP32, valid only in active tiles
+//   velocity     u[3][node]             FP32, valid only in active tiles
+//   tile stamps  stamp[tile]            step index at which a tile was last
+//                                       made active (8x8x8-node tiles)
+//   markers      pos[3][marker]         FP64 absolute, unwrapped
+//                U[3][marker], f[3][marker]  FP32
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbmib {
+
+constexpr int kQ = 19;
+constexpr int kTile = 8;       // active-tile edge in nodes
+constexpr int kScBlock = 256;  // stream-collide threads per block
+
+enum Forcing { kGuo = 0, kShanChen = 1 };
+enum Storage { kFp32 = 0, kFp16 = 1 };
+
+// One periodic box.  A single-box handle has exactly one.
+struct Box {
+  int nx, ny, nz;
+  int tx, ty, tz;       // tiles per axis (ceil(n / kTile))
+  int64_t node0;        // first node of the box in the population planes
+  int64_t n;            // nodes in the box
+  int tile0;            // first tile of the box in the stamp array
+  int block0;           // first stream-collide block of the box
+  int bead0, nbeads;    // beads of the box (contiguous)
+  int forcing;
+  float tau, omega;     // tau and 1/tau
+  float gx, gy, gz;     // uniform body force density
+};
+
+// Per-bead constant data.
+struct Bead {
+  int first, nv;        // markers [first, first+nv)
+  int tri0, ntri;       // triangles
+  int box, swimmer;
+  int slot;             // 0, 1, 2 within the swimmer
+  int tiles_x, tiles_y, tiles_z;  // reserved candidate tiles per axis
+  int tile_block0;      // first spread block of this bead
+  float ks, C, kt, kv;  // Skalak ks and C, Kantor-Nelson kt = 2 kb/sqrt 3, kv
+  double V0;            // stress-free volume
+};
+
+struct Swimmer {
+  int bead[3];
+  double k[2], L0[2];
+  double A, B, omega, alpha, phi0;
+};
+
+// Per-bead state recomputed every step.
+struct BeadState {
+  double c[3];          // centre (mean of nodes)
+  double V;             // enclosed volume
+  double fb[3];         // driving + spring force on the whole bead
+  int lo[3], hi[3];     // region: nodes [lo, hi] (unwrapped) within the kernel
+                        // support of some marker
+  int tlo[3], tcnt[3];  // region in tiles: first tile (unwrapped), count
+};
+
+// Everything a kernel needs, passed by value.
+struct Dev {
+  // lattice
+  void* pop[2];
+  int64_t pstride;
+  float* F;
+  float* u;
+  int* stamp;
+  const Box* boxes;
+  int nboxes;
+  const int* block_box;  // stream-collide block -> box
+  int64_t* step;         // device step counter
+  unsigned* done;        // last-block counter for the step tick
+  float fp16_scale, fp16_inv;
+  // markers and meshes
+  double* pos;           // [3][nm]
+  float* U;              // [3][nm]
+  float* fm;             // [3][nm]
+  int nm;
+  int width;             // delta kernel support in nodes
+  const Bead* beads;
+  int nbeads;
+  BeadState* bstate;
+  const Swimmer* swimmers;
+  int nswimmers;
+  const int* marker_bead;
+  // triangles: vertex ids and reference metric (FP64) / inverse (FP32)
+  const int* tri;        // [3][ntri]
+  const double* G0;      // [3][ntri]: G11, G12, G22
+  const float* G0inv;    // [3][ntri]
+  const float* A0;       // [ntri] reference area
+  const float* idetG0;   // [ntri] 1 / det G0
+  // hinges: x1, x2 shared edge, x3, x4 opposite; theta0 stress free
+  const int* hinge;      // [4][nh]
+  const double* theta0;
+  int ntri, nh;
+  // vertex -> incident triangles (tri*3 + corner) and hinges (h*4 + role)
+  const int* vt_off;
+  const int* vt;
+  const int* vh_off;
+  const int* vh;
+  int* overflow;         // set when a bead region outgrows its reserved tiles
+  int spread_blocks;
+  const int* spread_bead;  // spread block -> bead
+};
+
+// Launch wrappers (defined in the .hip files).
+void launch_stream_collide(const Dev& d, int storage, int nblocks, int tick, hipStream_t s);
+void launch_tick(const Dev& d, hipStream_t s);
+void launch_velocity(const Dev& d, int storage, int nblocks, float* u_out, float* rho_out,
+                     hipStream_t s);
+void launch_conserved(const Dev& d, int storage, double* partial, int nparts, double* out,
+                      hipStream_t s);
+void launch_bead_stats(const Dev& d, hipStream_t s);
+void launch_vertex_forces(const Dev& d, hipStream_t s);
+void launch_spread(const Dev& d, hipStream_t s);
+void launch_interp_advance(const Dev& d, hipStream_t s);
+void launch_bead_centres(const Dev& d, double* out, hipStream_t s);
+
+}  // namespace lbmib

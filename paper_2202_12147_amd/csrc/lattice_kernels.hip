@@ -1,0 +1,347 @@
+// Lattice kernels: fused pull stream-collide, macroscopic output, and the
+// FP64 conservation reductions.
+//
+// Fluid model (paper Sec. 2.1): D3Q19 BGK, Eq. (lbe) with the second-order
+// equilibrium of Eq. (lbm:equilibrium); moments rho = sum f, rho u_eq =
+// sum f c + tau F for the Shan-Chen force scheme (Eq. sc), physical velocity
+// rho u = sum f c + F/2.  The Guo scheme uses u in the equilibrium and adds
+// (1 - 1/(2 tau)) w_i [3 (c_i - u) + 9 (c_i.u) c_i].F.
+//
+// Storage holds g_i = f_i - w_i (deviation from the rest state), so the
+// O(1e-5) flow signal is not swamped by the O(1/3) weights in FP32; FP16
+// storage holds g_i * S rounded to nearest even.  Arithmetic is FP32.
+//
+// Streaming is "pull": node x gathers g*_i(x - c_i) from the source parity and
+// writes its 19 post-collision values to the same node of the other parity,
+// so every read and write of a wavefront covers consecutive x (coalesced);
+// only the c_x = +-1 loads are shifted by one element.
+#include <hip/hip_fp16.h>
+
+#include "common.h"
+
+namespace lbmib {
+
+namespace {
+
+constexpr float kW0 = 1.0f / 3.0f;
+constexpr float kW1 = 1.0f / 18.0f;
+constexpr float kW2 = 1.0f / 36.0f;
+
+template <int ST>
+struct PopIO;
+
+template <>
+struct PopIO<kFp32> {
+  using T = float;
+  __device__ static inline float ld(const float* p, float) { return *p; }
+  __device__ static inline void st(float* p, float v, float) { __builtin_nontemporal_store(v, p); }
+};
+
+template <>
+struct PopIO<kFp16> {
+  using T = __half;
+  __device__ static inline float ld(const __half* p, float inv) {
+    return __half2float(*p) * inv;
+  }
+  __device__ static inline void st(__half* p, float v, float scale) {
+    *p = __float2half_rn(v * scale);
+  }
+};
+
+// Offsets (in nodes, periodic wrap folded in) of the six face neighbours.
+struct Nbr {
+  int xm, xp, ym, yp, zm, zp;
+};
+
+__device__ inline Nbr neighbours(int x, int y, int z, int nx, int ny, int nz) {
+  const int sz = nx * ny;
+  Nbr o;
+  o.xm = (x == 0) ? nx - 1 : -1;
+  o.xp = (x == nx - 1) ? -(nx - 1) : 1;
+  o.ym = (y == 0) ? (ny - 1) * nx : -nx;
+  o.yp = (y == ny - 1) ? -(ny - 1) * nx : nx;
+  o.zm = (z == 0) ? (nz - 1) * sz : -sz;
+  o.zp = (z == nz - 1) ? -(nz - 1) * sz : sz;
+  return o;
+}
+
+// Pull the 19 deviations of node `id` (box-local) from the source planes.
+template <int ST>
+__device__ inline void pull(const typename PopIO<ST>::T* __restrict__ src, int64_t ps, int64_t base,
+                            const Nbr& o, float inv, float* g) {
+  using IO = PopIO<ST>;
+  const int off[kQ] = {0,
+                       o.xm, o.xp, o.ym, o.yp, o.zm, o.zp,
+                       o.xm + o.ym, o.xp + o.yp, o.xm + o.yp, o.xp + o.ym,
+                       o.xm + o.zm, o.xp + o.zp, o.xm + o.zp, o.xp + o.zm,
+                       o.ym + o.zm, o.yp + o.zp, o.ym + o.zp, o.yp + o.zm};
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) g[q] = IO::ld(src + q * ps + base + off[q], inv);
+}
+
+struct Moments {
+  float drho, rho, jx, jy, jz;
+};
+
+__device__ inline Moments moments(const float* g) {
+  Moments m;
+  float s = g[0];
+#pragma unroll
+  for (int q = 1; q < kQ; ++q) s += g[q];
+  m.drho = s;
+  m.rho = 1.0f + s;
+  m.jx = (g[1] - g[2]) + (g[7] - g[8]) + (g[9] - g[10]) + (g[11] - g[12]) + (g[13] - g[14]);
+  m.jy = (g[3] - g[4]) + (g[7] - g[8]) - (g[9] - g[10]) + (g[15] - g[16]) + (g[17] - g[18]);
+  m.jz = (g[5] - g[6]) + (g[11] - g[12]) - (g[13] - g[14]) + (g[15] - g[16]) - (g[17] - g[18]);
+  return m;
+}
+
+// BGK collision of one direction pair (+c, -c) with weight w.
+//   e    = c . u_eq, the equilibrium velocity projection
+//   cu,cf = c . u and c . F (Guo source), uf = u . F
+__device__ inline void collide_pair(float& gp, float& gm, float w, float om, float drho, float rho,
+                                    float usq15, float e, float src_a, float cu, float cf,
+                                    float uf) {
+  const float sym = w * (drho + rho * (4.5f * e * e - usq15));
+  const float asym = w * rho * 3.0f * e;
+  // Guo source: src_a (1 - om/2) w [3 (c - u).F + 9 (c.u)(c.F)], zero for Shan-Chen
+  const float s_sym = src_a * w * (-3.0f * uf + 9.0f * cu * cf);
+  const float s_asym = src_a * w * 3.0f * cf;
+  const float eqp = sym + asym, eqm = sym - asym;
+  gp = gp + om * (eqp - gp) + (s_sym + s_asym);
+  gm = gm + om * (eqm - gm) + (s_sym - s_asym);
+}
+
+template <int ST>
+__global__ __launch_bounds__(kScBlock) void k_stream_collide(Dev d, int tick) {
+  using IO = PopIO<ST>;
+  using T = typename IO::T;
+  const int blk = blockIdx.x;
+  const int b = d.nboxes == 1 ? 0 : d.block_box[blk];
+  const Box B = d.boxes[b];
+  const int64_t n = *d.step;
+  const int id = (blk - B.block0) * kScBlock + (int)threadIdx.x;
+  if (id < B.n) {
+    const int nx = B.nx, ny = B.ny, nz = B.nz;
+    const int x = id % nx;
+    const int yz = id / nx;
+    const int y = yz % ny;
+    const int z = yz / ny;
+    const Nbr o = neighbours(x, y, z, nx, ny, nz);
+    const T* __restrict__ src = static_cast<const T*>(d.pop[n & 1]);
+    T* __restrict__ dst = static_cast<T*>(d.pop[(n + 1) & 1]);
+    const int64_t ps = d.pstride;
+    const int64_t base = B.node0 + id;
+    float g[kQ];
+    pull<ST>(src, ps, base, o, d.fp16_inv, g);
+    const Moments m = moments(g);
+
+    float Fx = B.gx, Fy = B.gy, Fz = B.gz;
+    const int tile = B.tile0 + (x / kTile) + B.tx * ((y / kTile) + B.ty * (z / kTile));
+    const bool active = d.stamp[tile] == (int)n;
+    if (active) {
+      Fx += d.F[base];
+      Fy += d.F[ps + base];
+      Fz += d.F[2 * ps + base];
+    }
+    const float ir = 1.0f / m.rho;
+    const float ux = (m.jx + 0.5f * Fx) * ir;
+    const float uy = (m.jy + 0.5f * Fy) * ir;
+    const float uz = (m.jz + 0.5f * Fz) * ir;
+    if (active) {
+      d.u[base] = ux;
+      d.u[ps + base] = uy;
+      d.u[2 * ps + base] = uz;
+    }
+    float ex = ux, ey = uy, ez = uz, src_a = 1.0f - 0.5f * B.omega;
+    if (B.forcing == kShanChen) {
+      ex = (m.jx + B.tau * Fx) * ir;
+      ey = (m.jy + B.tau * Fy) * ir;
+      ez = (m.jz + B.tau * Fz) * ir;
+      src_a = 0.0f;
+    }
+    const float om = B.omega;
+    const float usq15 = 1.5f * (ex * ex + ey * ey + ez * ez);
+    const float uf = ux * Fx + uy * Fy + uz * Fz;
+    // rest population
+    {
+      const float eq0 = kW0 * (m.drho - m.rho * usq15);
+      g[0] = g[0] + om * (eq0 - g[0]) + src_a * kW0 * (-3.0f * uf);
+    }
+    // faces
+    collide_pair(g[1], g[2], kW1, om, m.drho, m.rho, usq15, ex, src_a, ux, Fx, uf);
+    collide_pair(g[3], g[4], kW1, om, m.drho, m.rho, usq15, ey, src_a, uy, Fy, uf);
+    collide_pair(g[5], g[6], kW1, om, m.drho, m.rho, usq15, ez, src_a, uz, Fz, uf);
+    // edges
+    collide_pair(g[7], g[8], kW2, om, m.drho, m.rho, usq15, ex + ey, src_a, ux + uy, Fx + Fy, uf);
+    collide_pair(g[9], g[10], kW2, om, m.drho, m.rho, usq15, ex - ey, src_a, ux - uy, Fx - Fy, uf);
+    collide_pair(g[11], g[12], kW2, om, m.drho, m.rho, usq15, ex + ez, src_a, ux + uz, Fx + Fz, uf);
+    collide_pair(g[13], g[14], kW2, om, m.drho, m.rho, usq15, ex - ez, src_a, ux - uz, Fx - Fz, uf);
+    collide_pair(g[15], g[16], kW2, om, m.drho, m.rho, usq15, ey + ez, src_a, uy + uz, Fy + Fz, uf);
+    collide_pair(g[17], g[18], kW2, om, m.drho, m.rho, usq15, ey - ez, src_a, uy - uz, Fy - Fz, uf);
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) IO::st(dst + q * ps + base, g[q], d.fp16_scale);
+  }
+  if (tick) {
+    // the last block to finish advances the step counter; every block has
+    // read it by then
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      __threadfence();
+      const unsigned prev = atomicAdd(d.done, 1u);
+      if (prev == gridDim.x - 1) {
+        atomicExch(d.done, 0u);
+        atomicExch(reinterpret_cast<unsigned long long*>(d.step),
+                   static_cast<unsigned long long>(n + 1));
+      }
+    }
+  }
+}
+
+__global__ void k_tick(int64_t* step) {
+  if (threadIdx.x == 0 && blockIdx.x == 0)
+    atomicAdd(reinterpret_cast<unsigned long long*>(step), 1ull);
+}
+
+// u_n and rho_n of the last completed step n = step - 1 (zero before any step).
+template <int ST>
+__global__ __launch_bounds__(kScBlock) void k_velocity(Dev d, float* __restrict__ uo,
+                                                        float* __restrict__ ro) {
+  using T = typename PopIO<ST>::T;
+  const int blk = blockIdx.x;
+  const int b = d.nboxes == 1 ? 0 : d.block_box[blk];
+  const Box B = d.boxes[b];
+  const int id = (blk - B.block0) * kScBlock + (int)threadIdx.x;
+  if (id >= B.n) return;
+  const int64_t c = *d.step;
+  // output planes are packed: total nodes of all boxes, box offset node0
+  // relative to the first box
+  const int64_t tot = d.boxes[d.nboxes - 1].node0 + d.boxes[d.nboxes - 1].n - d.boxes[0].node0;
+  const int64_t ob = B.node0 - d.boxes[0].node0 + id;
+  if (c == 0) {
+    if (uo) {
+      uo[ob] = 0.0f;
+      uo[tot + ob] = 0.0f;
+      uo[2 * tot + ob] = 0.0f;
+    }
+    if (ro) ro[ob] = 1.0f;
+    return;
+  }
+  const int64_t n = c - 1;
+  const int nx = B.nx, ny = B.ny, nz = B.nz;
+  const int x = id % nx;
+  const int yz = id / nx;
+  const int y = yz % ny;
+  const int z = yz / ny;
+  const Nbr o = neighbours(x, y, z, nx, ny, nz);
+  const T* src = static_cast<const T*>(d.pop[n & 1]);
+  const int64_t ps = d.pstride;
+  const int64_t base = B.node0 + id;
+  float g[kQ];
+  pull<ST>(src, ps, base, o, d.fp16_inv, g);
+  const Moments m = moments(g);
+  float Fx = B.gx, Fy = B.gy, Fz = B.gz;
+  const int tile = B.tile0 + (x / kTile) + B.tx * ((y / kTile) + B.ty * (z / kTile));
+  if (d.stamp[tile] == (int)n) {
+    Fx += d.F[base];
+    Fy += d.F[ps + base];
+    Fz += d.F[2 * ps + base];
+  }
+  const float ir = 1.0f / m.rho;
+  if (uo) {
+    uo[ob] = (m.jx + 0.5f * Fx) * ir;
+    uo[tot + ob] = (m.jy + 0.5f * Fy) * ir;
+    uo[2 * tot + ob] = (m.jz + 0.5f * Fz) * ir;
+  }
+  if (ro) ro[ob] = m.rho;
+}
+
+// Block sum of 4 doubles through wavefront shuffles, result in thread 0.
+__device__ inline void block_sum4(double* v) {
+  __shared__ double part[kScBlock / 64][4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    for (int s = 32; s > 0; s >>= 1) v[k] += __shfl_xor(v[k], s, 64);
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  if (lane == 0)
+    for (int k = 0; k < 4; ++k) part[wave][k] = v[k];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < 4; ++k) {
+      double s = 0;
+      for (int w = 0; w < kScBlock / 64; ++w) s += part[w][k];
+      v[k] = s;
+    }
+  }
+}
+
+// Stage 1: per-block FP64 sums of g and g c over the current state.
+template <int ST>
+__global__ __launch_bounds__(kScBlock) void k_conserved_partial(Dev d, double* __restrict__ part) {
+  using IO = PopIO<ST>;
+  using T = typename IO::T;
+  const int64_t c = *d.step;
+  const T* src = static_cast<const T*>(d.pop[c & 1]);
+  const int64_t ps = d.pstride;
+  double v[4] = {0, 0, 0, 0};
+  for (int b = 0; b < d.nboxes; ++b) {
+    const Box B = d.boxes[b];
+    for (int64_t id = (int64_t)blockIdx.x * kScBlock + threadIdx.x; id < B.n;
+         id += (int64_t)gridDim.x * kScBlock) {
+      float g[kQ];
+#pragma unroll
+      for (int q = 0; q < kQ; ++q) g[q] = IO::ld(src + q * ps + B.node0 + id, d.fp16_inv);
+      const Moments m = moments(g);
+      v[0] += (double)m.drho;
+      v[1] += (double)m.jx;
+      v[2] += (double)m.jy;
+      v[3] += (double)m.jz;
+    }
+  }
+  block_sum4(v);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 4; ++k) part[4 * blockIdx.x + k] = v[k];
+}
+
+// Stage 2: one block folds the partials in a fixed order.
+__global__ __launch_bounds__(kScBlock) void k_conserved_final(const double* __restrict__ part,
+                                                               int nparts, double* __restrict__ out) {
+  double v[4] = {0, 0, 0, 0};
+  for (int i = threadIdx.x; i < nparts; i += kScBlock)
+    for (int k = 0; k < 4; ++k) v[k] += part[4 * i + k];
+  block_sum4(v);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 4; ++k) out[k] = v[k];
+}
+
+}  // namespace
+
+void launch_stream_collide(const Dev& d, int storage, int nblocks, int tick, hipStream_t s) {
+  if (storage == kFp16)
+    hipLaunchKernelGGL(k_stream_collide<kFp16>, dim3(nblocks), dim3(kScBlock), 0, s, d, tick);
+  else
+    hipLaunchKernelGGL(k_stream_collide<kFp32>, dim3(nblocks), dim3(kScBlock), 0, s, d, tick);
+}
+
+void launch_tick(const Dev& d, hipStream_t s) {
+  hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, s, d.step);
+}
+
+void launch_velocity(const Dev& d, int storage, int nblocks, float* u_out, float* rho_out,
+                     hipStream_t s) {
+  if (storage == kFp16)
+    hipLaunchKernelGGL(k_velocity<kFp16>, dim3(nblocks), dim3(kScBlock), 0, s, d, u_out, rho_out);
+  else
+    hipLaunchKernelGGL(k_velocity<kFp32>, dim3(nblocks), dim3(kScBlock), 0, s, d, u_out, rho_out);
+}
+
+void launch_conserved(const Dev& d, int storage, double* partial, int nparts, double* out,
+                      hipStream_t s) {
+  if (storage == kFp16)
+    hipLaunchKernelGGL(k_conserved_partial<kFp16>, dim3(nparts), dim3(kScBlock), 0, s, d, partial);
+  else
+    hipLaunchKernelGGL(k_conserved_partial<kFp32>, dim3(nparts), dim3(kScBlock), 0, s, d, partial);
+  hipLaunchKernelGGL(k_conserved_final, dim3(1), dim3(kScBlock), 0, s, partial, nparts, out);
+}
+
+}  // namespace lbmib

@@ -1,0 +1,317 @@
+"""Thin Python binding of the lbmib C-ABI (include/lbmib.h).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+PyTorch supplies device memory (for on-device outputs) and the stream.  The
+binding refuses to run without the compiled library: there is no fallback.
+"""
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbmib.so")
+
+GUO, SHAN_CHEN = 0, 1
+FP32_SHIFTED, FP16_SHIFTED = 0, 1
+
+ERRORS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EDEVICE", -4: "LBM_ESTATE",
+          -5: "LBM_ENONFINITE", -6: "LBM_EIO", -7: "LBM_EOVERFLOW"}
+
+# every symbol the header declares (checked by the CPU tests)
+SYMBOLS = [
+    "lbm_create", "lbm_destroy", "lbm_swimmer_add", "lbm_set_body_force", "lbm_step", "lbm_sync",
+    "lbm_time", "lbm_n_markers", "lbm_n_swimmers", "lbm_get_swimmer_centres",
+    "lbm_get_bead_centres", "lbm_get_markers", "lbm_get_marker_velocities",
+    "lbm_get_marker_forces", "lbm_get_velocity",
+    "lbm_get_density", "lbm_get_conserved", "lbm_set_populations", "lbm_get_populations",
+    "lbm_save", "lbm_load", "lbm_set_kernel_timing", "lbm_kernel_time", "lbm_bytes_per_step",
+    "lbm_strerror", "lbm_last_error",
+]
+
+
+class LbmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Grid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32)]
+
+
+class Opts(C.Structure):
+    _fields_ = [("storage", C.c_int32), ("delta_width", C.c_int32), ("fp16_scale", C.c_float),
+                ("use_graphs", C.c_int32), ("stream", C.c_void_p)]
+
+
+class BeadDesc(C.Structure):
+    _fields_ = [("centre", C.c_double * 3), ("radius", C.c_double), ("level", C.c_int32),
+                ("kappa_s", C.c_double), ("C", C.c_double), ("kappa_b", C.c_double),
+                ("kappa_v", C.c_double)]
+
+
+class SpringDesc(C.Structure):
+    _fields_ = [("k", C.c_double), ("L0", C.c_double)]
+
+
+class ActuationDesc(C.Structure):
+    _fields_ = [("A", C.c_double), ("B", C.c_double), ("period", C.c_double),
+                ("alpha", C.c_double), ("phi0", C.c_double)]
+
+
+_lib = None
+
+
+def load_library():
+    """Load liblbmib.so; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -c 'import __graft_entry__ as g; g.build()'`")
+    # torch owns the process's HIP runtime: load it first so that the
+    # library's libamdhip64.so.7 dependency resolves to torch's copy instead
+    # of mapping a second runtime next to it
+    import torch  # noqa: F401
+    lib = C.CDLL(LIB_PATH)
+    runtimes = _hip_runtimes()
+    if len(runtimes) > 1:
+        raise RuntimeError(f"two HIP runtimes are mapped in this process: {sorted(runtimes)}")
+    vp, i32, i64, dp, fp = C.c_void_p, C.c_int32, C.c_int64, C.c_void_p, C.c_void_p
+    sig = {
+        "lbm_create": (C.c_int, [C.POINTER(Grid), C.c_double, C.c_int, C.POINTER(Opts),
+                                 C.POINTER(C.c_void_p)]),
+        "lbm_destroy": (C.c_int, [vp]),
+        "lbm_swimmer_add": (C.c_int, [vp, C.POINTER(BeadDesc), C.POINTER(SpringDesc),
+                                      C.POINTER(ActuationDesc), C.POINTER(i32)]),
+        "lbm_set_body_force": (C.c_int, [vp, dp]),
+        "lbm_step": (C.c_int, [vp, i64]),
+        "lbm_sync": (C.c_int, [vp]),
+        "lbm_time": (i64, [vp]),
+        "lbm_n_markers": (i32, [vp]),
+        "lbm_n_swimmers": (i32, [vp]),
+        "lbm_get_swimmer_centres": (C.c_int, [vp, dp]),
+        "lbm_get_bead_centres": (C.c_int, [vp, dp]),
+        "lbm_get_markers": (C.c_int, [vp, dp]),
+        "lbm_get_marker_velocities": (C.c_int, [vp, dp]),
+        "lbm_get_marker_forces": (C.c_int, [vp, dp]),
+        "lbm_get_velocity": (C.c_int, [vp, fp, C.c_int]),
+        "lbm_get_density": (C.c_int, [vp, fp, C.c_int]),
+        "lbm_get_conserved": (C.c_int, [vp, dp]),
+        "lbm_set_populations": (C.c_int, [vp, dp]),
+        "lbm_get_populations": (C.c_int, [vp, dp]),
+        "lbm_save": (C.c_int, [vp, C.c_char_p]),
+        "lbm_load": (C.c_int, [vp, C.c_char_p]),
+        "lbm_set_kernel_timing": (C.c_int, [vp, C.c_int]),
+        "lbm_kernel_time": (C.c_int, [vp, C.POINTER(C.c_double), C.POINTER(i64)]),
+        "lbm_bytes_per_step": (i64, [vp]),
+        "lbm_strerror": (C.c_char_p, [C.c_int]),
+        "lbm_last_error": (C.c_char_p, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _hip_runtimes():
+    """Distinct libamdhip64 files mapped into this process."""
+    paths = set()
+    try:
+        with open("/proc/self/maps") as f:
+            for line in f:
+                if "libamdhip64" in line:
+                    paths.add(os.path.realpath(line.split()[-1]))
+    except OSError:
+        pass
+    return paths
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+class Lattice:
+    """One periodic D3Q19 box with swimmers, stepped by the HIP library.
+
+    ``stream``: a ``torch.cuda.Stream`` (or raw hipStream_t int) to enqueue on;
+    None lets the library create its own."""
+
+    def __init__(self, shape, tau, forcing=GUO, storage=FP32_SHIFTED, width=3, fp16_scale=1.0,
+                 use_graphs=True, stream=None):
+        self.lib = load_library()
+        self.shape = tuple(int(s) for s in shape)
+        self.storage = storage
+        raw = None
+        if stream is not None:
+            raw = getattr(stream, "cuda_stream", stream)
+            raw = int(raw) or None
+        g = Grid(*self.shape)
+        o = Opts(int(storage), int(width), float(fp16_scale), int(bool(use_graphs)), raw)
+        h = C.c_void_p()
+        rc = self.lib.lbm_create(C.byref(g), float(tau), int(forcing), C.byref(o), C.byref(h))
+        if rc:
+            raise LbmError(rc, self.lib.lbm_strerror(rc).decode())
+        self.h = h
+
+    # -- helpers
+    def _check(self, rc):
+        if rc:
+            raise LbmError(rc, self.lib.lbm_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.lbm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def N(self):
+        nx, ny, nz = self.shape
+        return nx * ny * nz
+
+    # -- setup
+    def add_swimmer(self, sw):
+        """Add a swimmer described by a ``workloads.swimmer`` dict."""
+        beads = (BeadDesc * 3)()
+        for k in range(3):
+            beads[k].centre[:] = [float(v) for v in sw["centres"][k]]
+            beads[k].radius = float(sw["radius"][k])
+            beads[k].level = int(sw["level"])
+            beads[k].kappa_s = float(sw["ks"])
+            beads[k].C = float(sw["C"])
+            beads[k].kappa_b = float(sw["kb"])
+            beads[k].kappa_v = float(sw["kv"])
+        springs = (SpringDesc * 2)(SpringDesc(float(sw["k"][0]), float(sw["L0"][0])),
+                                   SpringDesc(float(sw["k"][1]), float(sw["L0"][1])))
+        act = ActuationDesc(float(sw["A"]), float(sw["B"]), float(sw["T"]), float(sw["alpha"]),
+                            float(sw["phi0"]))
+        sid = C.c_int32()
+        self._check(self.lib.lbm_swimmer_add(self.h, beads, springs, C.byref(act), C.byref(sid)))
+        return sid.value
+
+    def set_body_force(self, g):
+        g = np.ascontiguousarray(g, np.float64)
+        self._check(self.lib.lbm_set_body_force(self.h, _ptr(g)))
+
+    def set_populations(self, dev):
+        dev = np.ascontiguousarray(dev, np.float64)
+        assert dev.size == 19 * self.N
+        self._check(self.lib.lbm_set_populations(self.h, _ptr(dev)))
+
+    # -- stepping
+    def step(self, n=1):
+        self._check(self.lib.lbm_step(self.h, int(n)))
+
+    def sync(self):
+        self._check(self.lib.lbm_sync(self.h))
+
+    @property
+    def time(self):
+        return self.lib.lbm_time(self.h)
+
+    @property
+    def n_markers(self):
+        return self.lib.lbm_n_markers(self.h)
+
+    @property
+    def n_swimmers(self):
+        return self.lib.lbm_n_swimmers(self.h)
+
+    # -- observables
+    def swimmer_centres(self):
+        out = np.zeros((self.n_swimmers, 3))
+        self._check(self.lib.lbm_get_swimmer_centres(self.h, _ptr(out)))
+        return out
+
+    def bead_centres(self):
+        out = np.zeros((3 * self.n_swimmers, 3))
+        self._check(self.lib.lbm_get_bead_centres(self.h, _ptr(out)))
+        return out
+
+    def markers(self):
+        out = np.zeros((self.n_markers, 3))
+        self._check(self.lib.lbm_get_markers(self.h, _ptr(out)))
+        return out
+
+    def marker_velocities(self):
+        out = np.zeros((self.n_markers, 3))
+        self._check(self.lib.lbm_get_marker_velocities(self.h, _ptr(out)))
+        return out
+
+    def marker_forces(self):
+        out = np.zeros((self.n_markers, 3))
+        self._check(self.lib.lbm_get_marker_forces(self.h, _ptr(out)))
+        return out
+
+    def velocity(self, device=None):
+        """u of the last step, [3, nz, ny, nx] float32: numpy on the host, or a
+        torch tensor on ``device`` (e.g. "cuda:0")."""
+        nx, ny, nz = self.shape
+        if device is not None:
+            import torch
+            t = torch.empty((3, nz, ny, nx), dtype=torch.float32, device=device)
+            self._check(self.lib.lbm_get_velocity(self.h, C.c_void_p(t.data_ptr()), 1))
+            return t
+        out = np.zeros((3, nz, ny, nx), np.float32)
+        self._check(self.lib.lbm_get_velocity(self.h, _ptr(out), 0))
+        return out
+
+    def density(self):
+        nx, ny, nz = self.shape
+        out = np.zeros((nz, ny, nx), np.float32)
+        self._check(self.lib.lbm_get_density(self.h, _ptr(out), 0))
+        return out
+
+    def conserved(self):
+        out = np.zeros(4)
+        self._check(self.lib.lbm_get_conserved(self.h, _ptr(out)))
+        return out
+
+    def populations(self):
+        nx, ny, nz = self.shape
+        out = np.zeros((19, nz, ny, nx))
+        self._check(self.lib.lbm_get_populations(self.h, _ptr(out)))
+        return out
+
+    def save(self, path):
+        self._check(self.lib.lbm_save(self.h, str(path).encode()))
+
+    def load(self, path):
+        self._check(self.lib.lbm_load(self.h, str(path).encode()))
+
+    # -- measurement
+    def set_kernel_timing(self, on):
+        self._check(self.lib.lbm_set_kernel_timing(self.h, int(bool(on))))
+
+    def kernel_time(self):
+        ms, n = C.c_double(), C.c_int64()
+        self._check(self.lib.lbm_kernel_time(self.h, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+    @property
+    def bytes_per_step(self):
+        return self.lib.lbm_bytes_per_step(self.h)
+
+
+def from_workload(case, storage=FP32_SHIFTED, fp16_scale=1.0, use_graphs=True, stream=None):
+    """Build a Lattice with the swimmers of a ``workloads`` case dict."""
+    lat = Lattice(case["shape"], case["tau"], case["forcing"], storage, case["width"], fp16_scale,
+                  use_graphs, stream)
+    for sw in case.get("swimmers", []):
+        lat.add_swimmer(sw)
+    return lat
+
+
+def mlups(nodes, steps, seconds):
+    return nodes * steps / seconds / 1e6 if seconds > 0 else math.nan

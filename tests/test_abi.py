@@ -1,0 +1,53 @@
+"""CPU checks of the C-ABI boundary: the library loads, exports exactly what
+include/lbmib.h declares, and rejects invalid arguments before touching the
+GPU."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2202_12147_amd import lbmib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "lbmib.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_header_and_binding_agree():
+    assert _declared() == sorted(lbmib.SYMBOLS)
+
+
+def test_library_exports_every_symbol():
+    lib = lbmib.load_library()
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_invalid_arguments_rejected():
+    lib = lbmib.load_library()
+    h = C.c_void_p()
+    ok = lbmib.Grid(32, 32, 32)
+    assert lib.lbm_create(C.byref(ok), 0.5, 0, None, C.byref(h)) == -1  # tau <= 1/2
+    assert lib.lbm_create(C.byref(ok), float("nan"), 0, None, C.byref(h)) == -1
+    assert lib.lbm_create(C.byref(lbmib.Grid(8, 32, 32)), 1.0, 0, None, C.byref(h)) == -1
+    assert lib.lbm_create(C.byref(ok), 1.0, 7, None, C.byref(h)) == -1  # bad forcing
+    bad = lbmib.Opts(0, 5, 1.0, 1, None)
+    assert lib.lbm_create(C.byref(ok), 1.0, 0, C.byref(bad), C.byref(h)) == -1  # width 5
+    bad = lbmib.Opts(1, 3, 3.0, 1, None)
+    assert lib.lbm_create(C.byref(ok), 1.0, 0, C.byref(bad), C.byref(h)) == -1  # scale not 2^k
+    assert lib.lbm_create(None, 1.0, 0, None, C.byref(h)) == -1
+    assert h.value is None
+    assert lib.lbm_strerror(-1) == b"invalid argument"
+    assert lib.lbm_destroy(None) == 0
+
+
+def test_binding_refuses_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(lbmib, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(lbmib, "_lib", None)
+    with pytest.raises(RuntimeError):
+        lbmib.load_library()
