@@ -191,9 +191,20 @@ int lbm_load(lbm_handle* h, const char* path);
  * summed kernel time (ms) and launch count since timing was switched on. */
 int lbm_set_kernel_timing(lbm_handle* h, int on);
 int lbm_kernel_time(lbm_handle* h, double* ms, int64_t* launches);
+/* Launch shape of the stream-collide kernel: workgroup size 128, 256 or 512
+ * nodes, and whether workgroups are remapped so that each of the 8 XCDs
+ * streams one contiguous range of the grid.  Results are bitwise identical
+ * for every shape.  Errors: LBM_EINVAL. */
+int lbm_set_stream_collide_launch(lbm_handle* h, int block, int xcd_remap);
 /* Algorithmic bytes one stream-collide launch moves (19 populations read and
  * written once per node at the storage width). */
 int64_t lbm_bytes_per_step(const lbm_handle* h);
+
+/* Achievable device-memory bandwidth: times `iters` launches of a plain copy
+ * kernel between two fresh device buffers of `bytes` each (allocated and freed
+ * here) and writes read+write bytes per second / 1e9 to *gbs.  Errors:
+ * LBM_EINVAL (bytes < 16 KiB, iters < 1), LBM_ENOMEM, LBM_EDEVICE. */
+int lbm_probe_copy_bandwidth(int64_t bytes, int iters, double* gbs);
 
 /* ---- errors ---------------------------------------------------------------- */
 const char* lbm_strerror(int code);

@@ -30,7 +30,7 @@ struct Box {
   int64_t node0;        // first node of the box in the population planes
   int64_t n;            // nodes in the box
   int tile0;            // first tile of the box in the stamp array
-  int block0;           // first stream-collide block of the box
+  int block0;           // first 256-node block of the box
   int bead0, nbeads;    // beads of the box (contiguous)
   int forcing;
   float tau, omega;     // tau and 1/tau
@@ -59,7 +59,6 @@ struct Swimmer {
 struct BeadState {
   double c[3];          // centre (mean of nodes)
   double V;             // enclosed volume
-  double fb[3];         // driving + spring force on the whole bead
   int lo[3], hi[3];     // region: nodes [lo, hi] (unwrapped) within the kernel
                         // support of some marker
   int tlo[3], tcnt[3];  // region in tiles: first tile (unwrapped), count
@@ -75,7 +74,9 @@ struct Dev {
   int* stamp;
   const Box* boxes;
   int nboxes;
-  const int* block_box;  // stream-collide block -> box
+  const int* block_box;  // 256-node block -> box (output and reduction kernels)
+  const int* sc_block_box;   // stream-collide block -> box (tuned block size)
+  const int* sc_box_block0;  // first stream-collide block of each box
   int64_t* step;         // device step counter
   unsigned* done;        // last-block counter for the step tick
   float fp16_scale, fp16_inv;
@@ -97,9 +98,10 @@ struct Dev {
   const float* G0inv;    // [3][ntri]
   const float* A0;       // [ntri] reference area
   const float* idetG0;   // [ntri] 1 / det G0
-  // hinges: x1, x2 shared edge, x3, x4 opposite; theta0 stress free
+  // hinges: x1, x2 shared edge, x3, x4 opposite; stress-free dihedral angle
+  // theta0 as (cos theta0, sin theta0)
   const int* hinge;      // [4][nh]
-  const double* theta0;
+  const double* th0cs;   // [2][nh]
   int ntri, nh;
   // vertex -> incident triangles (tri*3 + corner) and hinges (h*4 + role)
   const int* vt_off;
@@ -112,7 +114,8 @@ struct Dev {
 };
 
 // Launch wrappers (defined in the .hip files).
-void launch_stream_collide(const Dev& d, int storage, int nblocks, int tick, hipStream_t s);
+void launch_stream_collide(const Dev& d, int storage, int block, int nblocks, int tick, int remap,
+                           hipStream_t s);
 void launch_tick(const Dev& d, hipStream_t s);
 void launch_velocity(const Dev& d, int storage, int nblocks, float* u_out, float* rho_out,
                      hipStream_t s);
@@ -123,5 +126,6 @@ void launch_vertex_forces(const Dev& d, hipStream_t s);
 void launch_spread(const Dev& d, hipStream_t s);
 void launch_interp_advance(const Dev& d, hipStream_t s);
 void launch_bead_centres(const Dev& d, double* out, hipStream_t s);
+void launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t s);
 
 }  // namespace lbmib

@@ -36,7 +36,7 @@ namespace lbmib {
 
 namespace {
 
-constexpr int kStatsBlock = 256;
+constexpr int kStatsBlock = 1024;
 constexpr int kSpreadBlock = kTile * kTile * kTile;  // 512, one thread per node
 constexpr int kInterpBlock = 256;
 
@@ -89,142 +89,124 @@ __device__ inline double block_sum(double v, double* sh) {
   for (int i = 0; i < BS / 64; ++i) t += sh[i];
   return t;
 }
-template <int BS>
-__device__ inline double block_min(double v, double* sh) {
-  for (int s = 32; s > 0; s >>= 1) v = fmin(v, __shfl_xor(v, s, 64));
-  const int w = threadIdx.x / 64, l = threadIdx.x % 64;
-  __syncthreads();
-  if (l == 0) sh[w] = v;
-  __syncthreads();
-  double t = sh[0];
-  for (int i = 1; i < BS / 64; ++i) t = fmin(t, sh[i]);
-  return t;
-}
-template <int BS>
-__device__ inline double block_max(double v, double* sh) {
-  for (int s = 32; s > 0; s >>= 1) v = fmax(v, __shfl_xor(v, s, 64));
-  const int w = threadIdx.x / 64, l = threadIdx.x % 64;
-  __syncthreads();
-  if (l == 0) sh[w] = v;
-  __syncthreads();
-  double t = sh[0];
-  for (int i = 1; i < BS / 64; ++i) t = fmax(t, sh[i]);
-  return t;
-}
-
 // ---- bead statistics ----------------------------------------------------------
+// One workgroup per bead: centre (mean of nodes), bounding box and enclosed
+// volume, reduced in FP64 with wavefront shuffles, and from the box the node
+// region the bead's stencils can touch (in 8^3 tiles).
 template <int NW>
 __global__ __launch_bounds__(kStatsBlock) void k_bead_stats(Dev d) {
-  __shared__ double sh[kStatsBlock / 64];
-  __shared__ double cen[3][3];
-  const Swimmer S = d.swimmers[blockIdx.x];
-  const int64_t n = *d.step;
-  for (int k = 0; k < 3; ++k) {
-    const int b = S.bead[k];
-    const Bead Bd = d.beads[b];
-    double sx = 0, sy = 0, sz = 0;
-    double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
-    for (int i = threadIdx.x; i < Bd.nv; i += kStatsBlock) {
-      const double3 p = load_pos(d.pos, d.nm, Bd.first + i);
-      sx += p.x;
-      sy += p.y;
-      sz += p.z;
-      mn[0] = fmin(mn[0], p.x);
-      mn[1] = fmin(mn[1], p.y);
-      mn[2] = fmin(mn[2], p.z);
-      mx[0] = fmax(mx[0], p.x);
-      mx[1] = fmax(mx[1], p.y);
-      mx[2] = fmax(mx[2], p.z);
-    }
-    const double inv = 1.0 / Bd.nv;
-    const double c[3] = {block_sum<kStatsBlock>(sx, sh) * inv, block_sum<kStatsBlock>(sy, sh) * inv,
-                         block_sum<kStatsBlock>(sz, sh) * inv};
-    double lo[3], hi[3];
-    for (int a = 0; a < 3; ++a) {
-      lo[a] = block_min<kStatsBlock>(mn[a], sh);
-      hi[a] = block_max<kStatsBlock>(mx[a], sh);
-    }
-    // enclosed volume, relative to the centre
-    double v = 0;
-    for (int t = threadIdx.x; t < Bd.ntri; t += kStatsBlock) {
-      const int tt = Bd.tri0 + t;
-      const double3 p0 = load_pos(d.pos, d.nm, d.tri[tt]);
-      const double3 p1 = load_pos(d.pos, d.nm, d.tri[d.ntri + tt]);
-      const double3 p2 = load_pos(d.pos, d.nm, d.tri[2 * d.ntri + tt]);
-      const double ax = p0.x - c[0], ay = p0.y - c[1], az = p0.z - c[2];
-      const double bx = p1.x - c[0], by = p1.y - c[1], bz = p1.z - c[2];
-      const double qx = p2.x - c[0], qy = p2.y - c[1], qz = p2.z - c[2];
-      v += ax * (by * qz - bz * qy) + ay * (bz * qx - bx * qz) + az * (bx * qy - by * qx);
-    }
-    v = block_sum<kStatsBlock>(v, sh) / 6.0;
-    if (threadIdx.x == 0) {
-      BeadState& st = d.bstate[b];
-      const Box B = d.boxes[Bd.box];
-      const int T[3] = {B.tx, B.ty, B.tz};
-      const int reserved[3] = {Bd.tiles_x, Bd.tiles_y, Bd.tiles_z};
-      for (int a = 0; a < 3; ++a) {
-        st.c[a] = c[a];
-        cen[k][a] = c[a];
-        st.lo[a] = stencil_base<NW>(lo[a]);
-        st.hi[a] = stencil_base<NW>(hi[a]) + NW - 1;
-        int t0 = floor_div(st.lo[a], kTile);
-        int cnt = floor_div(st.hi[a], kTile) - t0 + 1;
-        if (cnt >= T[a]) {
-          t0 = 0;
-          cnt = T[a];
-        }
-        if (cnt > reserved[a]) {
-          atomicOr(d.overflow, 1);
-          cnt = reserved[a];
-        }
-        st.tlo[a] = t0;
-        st.tcnt[a] = cnt;
-      }
-      st.V = v;
-    }
-    __syncthreads();
+  constexpr int NWAVE = kStatsBlock / 64;
+  __shared__ double part[NWAVE][9];
+  __shared__ double cen[3];
+  const int b = blockIdx.x;
+  const Bead Bd = d.beads[b];
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  double v[9] = {0, 0, 0, 1e300, 1e300, 1e300, -1e300, -1e300, -1e300};
+  for (int i = threadIdx.x; i < Bd.nv; i += kStatsBlock) {
+    const double3 p = load_pos(d.pos, d.nm, Bd.first + i);
+    v[0] += p.x;
+    v[1] += p.y;
+    v[2] += p.z;
+    v[3] = fmin(v[3], p.x);
+    v[4] = fmin(v[4], p.y);
+    v[5] = fmin(v[5], p.z);
+    v[6] = fmax(v[6], p.x);
+    v[7] = fmax(v[7], p.y);
+    v[8] = fmax(v[8], p.z);
   }
-  // driving forces (Sec. 2.2, Eq. ext forces) and harmonic springs between
-  // bead centres: f1 = -k (|R1-R2| - L) (R1-R2)/|R1-R2|, f2 = -f1 - f3
+#pragma unroll
+  for (int s = 32; s > 0; s >>= 1) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) v[k] += __shfl_xor(v[k], s, 64);
+#pragma unroll
+    for (int k = 3; k < 6; ++k) v[k] = fmin(v[k], __shfl_xor(v[k], s, 64));
+#pragma unroll
+    for (int k = 6; k < 9; ++k) v[k] = fmax(v[k], __shfl_xor(v[k], s, 64));
+  }
+  if (lane == 0)
+    for (int k = 0; k < 9; ++k) part[wave][k] = v[k];
+  __syncthreads();
   if (threadIdx.x == 0) {
-    const double t = (double)n;
-    const double f1 = S.A * sin(S.omega * t + S.phi0);
-    const double f3 = S.B * sin(S.omega * t + S.phi0 + S.alpha);
-    double fb[3][3] = {{f1, 0, 0}, {-f1 - f3, 0, 0}, {f3, 0, 0}};
-    for (int sp = 0; sp < 2; ++sp) {
-      const int outer = sp == 0 ? 0 : 2;
-      const double dx = cen[outer][0] - cen[1][0], dy = cen[outer][1] - cen[1][1],
-                   dz = cen[outer][2] - cen[1][2];
-      const double len = sqrt(dx * dx + dy * dy + dz * dz);
-      const double s = -S.k[sp] * (len - S.L0[sp]) / len;
-      fb[outer][0] += s * dx;
-      fb[outer][1] += s * dy;
-      fb[outer][2] += s * dz;
-      fb[1][0] -= s * dx;
-      fb[1][1] -= s * dy;
-      fb[1][2] -= s * dz;
+    for (int w = 1; w < NWAVE; ++w) {
+      for (int k = 0; k < 3; ++k) part[0][k] += part[w][k];
+      for (int k = 3; k < 6; ++k) part[0][k] = fmin(part[0][k], part[w][k]);
+      for (int k = 6; k < 9; ++k) part[0][k] = fmax(part[0][k], part[w][k]);
     }
-    for (int k = 0; k < 3; ++k)
-      for (int a = 0; a < 3; ++a) d.bstate[S.bead[k]].fb[a] = fb[k][a];
+    for (int k = 0; k < 3; ++k) cen[k] = part[0][k] / Bd.nv;
+  }
+  __syncthreads();
+  const double cx = cen[0], cy = cen[1], cz = cen[2];
+  // enclosed volume 1/6 sum (r0-c).((r1-c) x (r2-c)) over outward triangles
+  double vol = 0;
+  for (int t = threadIdx.x; t < Bd.ntri; t += kStatsBlock) {
+    const int tt = Bd.tri0 + t;
+    const double3 p0 = load_pos(d.pos, d.nm, d.tri[tt]);
+    const double3 p1 = load_pos(d.pos, d.nm, d.tri[d.ntri + tt]);
+    const double3 p2 = load_pos(d.pos, d.nm, d.tri[2 * d.ntri + tt]);
+    const double ax = p0.x - cx, ay = p0.y - cy, az = p0.z - cz;
+    const double bx = p1.x - cx, by = p1.y - cy, bz = p1.z - cz;
+    const double qx = p2.x - cx, qy = p2.y - cy, qz = p2.z - cz;
+    vol += ax * (by * qz - bz * qy) + ay * (bz * qx - bx * qz) + az * (bx * qy - by * qx);
+  }
+  for (int s = 32; s > 0; s >>= 1) vol += __shfl_xor(vol, s, 64);
+  __syncthreads();
+  if (lane == 0) part[wave][0] = vol;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double V = 0;
+    for (int w = 0; w < NWAVE; ++w) V += part[w][0];
+    BeadState& st = d.bstate[b];
+    const Box B = d.boxes[Bd.box];
+    const int T[3] = {B.tx, B.ty, B.tz};
+    const int reserved[3] = {Bd.tiles_x, Bd.tiles_y, Bd.tiles_z};
+    const double lo[3] = {part[0][3], part[0][4], part[0][5]};
+    const double hi[3] = {part[0][6], part[0][7], part[0][8]};
+    st.c[0] = cx;
+    st.c[1] = cy;
+    st.c[2] = cz;
+    st.V = V / 6.0;
+    for (int a = 0; a < 3; ++a) {
+      st.lo[a] = stencil_base<NW>(lo[a]);
+      st.hi[a] = stencil_base<NW>(hi[a]) + NW - 1;
+      int t0 = floor_div(st.lo[a], kTile);
+      int cnt = floor_div(st.hi[a], kTile) - t0 + 1;
+      if (cnt >= T[a]) {
+        t0 = 0;
+        cnt = T[a];
+      }
+      if (cnt > reserved[a]) {
+        atomicOr(d.overflow, 1);
+        cnt = reserved[a];
+      }
+      if (cnt < 0) cnt = 0;
+      st.tlo[a] = t0;
+      st.tcnt[a] = cnt;
+    }
   }
 }
 
 // ---- membrane forces ------------------------------------------------------------
-// Skalak force on corner `corner` of triangle t.  With Delta = g - G0 (metric
-// change, formed in FP64), I1 = G0^-1 : Delta, I2 = (det g - det G0)/det G0 and
-// the stress P = dW/dg written so that the O(1) parts cancel analytically:
-// P = ks A0/4 [(2 I1 + 2 C I2) G0^-1 + (2 C I2 - 2) adj(Delta)/det G0].
-__device__ inline float3 skalak_corner(const Dev& d, const Bead& Bd, int t, int corner) {
+// Skalak + volume-penalty force on corner `corner` of triangle t.  With
+// Delta = g - G0 (metric change, formed in FP64), I1 = G0^-1 : Delta,
+// I2 = (det g - det G0)/det G0 and the stress P = dW/dg written so that its
+// O(1) parts cancel analytically:
+//   P = ks A0/4 [(2 I1 + 2 C I2) G0^-1 + (2 C I2 - 2) adj(Delta)/det G0],
+// dW/de1 = 2 (P11 e1 + P12 e2), dW/de2 = 2 (P12 e1 + P22 e2), e_a = r_a - r_0.
+// Volume: f = -pv * (r_b - c) x (r_c - c) with (corner, b, c) counter-clockwise
+// and pv = kv (V - V0)/(6 V0).
+__device__ inline float3 triangle_corner(const Dev& d, const Bead& Bd, int t, int corner,
+                                         const double* c, float pv) {
   const int i0 = d.tri[t], i1 = d.tri[d.ntri + t], i2 = d.tri[2 * d.ntri + t];
   const double3 p0 = load_pos(d.pos, d.nm, i0);
   const double3 p1 = load_pos(d.pos, d.nm, i1);
   const double3 p2 = load_pos(d.pos, d.nm, i2);
   const double e1x = p1.x - p0.x, e1y = p1.y - p0.y, e1z = p1.z - p0.z;
   const double e2x = p2.x - p0.x, e2y = p2.y - p0.y, e2z = p2.z - p0.z;
-  const float D11 = (float)(e1x * e1x + e1y * e1y + e1z * e1z - d.G0[t]);
-  const float D12 = (float)(e1x * e2x + e1y * e2y + e1z * e2z - d.G0[d.ntri + t]);
-  const float D22 = (float)(e2x * e2x + e2y * e2y + e2z * e2z - d.G0[2 * d.ntri + t]);
-  const float G11 = (float)d.G0[t], G12 = (float)d.G0[d.ntri + t], G22 = (float)d.G0[2 * d.ntri + t];
+  const double G11d = d.G0[t], G12d = d.G0[d.ntri + t], G22d = d.G0[2 * d.ntri + t];
+  const float D11 = (float)(e1x * e1x + e1y * e1y + e1z * e1z - G11d);
+  const float D12 = (float)(e1x * e2x + e1y * e2y + e1z * e2z - G12d);
+  const float D22 = (float)(e2x * e2x + e2y * e2y + e2z * e2z - G22d);
+  const float G11 = (float)G11d, G12 = (float)G12d, G22 = (float)G22d;
   const float Gi11 = d.G0inv[t], Gi12 = d.G0inv[d.ntri + t], Gi22 = d.G0inv[2 * d.ntri + t];
   const float idet = d.idetG0[t];
   const float I1 = Gi11 * D11 + 2.0f * Gi12 * D12 + Gi22 * D22;
@@ -235,26 +217,37 @@ __device__ inline float3 skalak_corner(const Dev& d, const Bead& Bd, int t, int 
   const float P11 = a * Gi11 + bq * D22;
   const float P12 = a * Gi12 - bq * D12;
   const float P22 = a * Gi22 + bq * D11;
-  const float3 e1 = make_float3((float)e1x, (float)e1y, (float)e1z);
-  const float3 e2 = make_float3((float)e2x, (float)e2y, (float)e2z);
-  // dW/de1 = 2 (P11 e1 + P12 e2), dW/de2 = 2 (P12 e1 + P22 e2); e_a = r_a - r_0
-  if (corner == 1)
-    return make_float3(-2.0f * (P11 * e1.x + P12 * e2.x), -2.0f * (P11 * e1.y + P12 * e2.y),
-                       -2.0f * (P11 * e1.z + P12 * e2.z));
-  if (corner == 2)
-    return make_float3(-2.0f * (P12 * e1.x + P22 * e2.x), -2.0f * (P12 * e1.y + P22 * e2.y),
-                       -2.0f * (P12 * e1.z + P22 * e2.z));
-  return make_float3(2.0f * ((P11 + P12) * e1.x + (P12 + P22) * e2.x),
-                     2.0f * ((P11 + P12) * e1.y + (P12 + P22) * e2.y),
-                     2.0f * ((P11 + P12) * e1.z + (P12 + P22) * e2.z));
+  const float e1[3] = {(float)e1x, (float)e1y, (float)e1z};
+  const float e2[3] = {(float)e2x, (float)e2y, (float)e2z};
+  float ca, cb;  // force = -(ca e1 + cb e2) from the Skalak energy
+  if (corner == 1) {
+    ca = 2.0f * P11;
+    cb = 2.0f * P12;
+  } else if (corner == 2) {
+    ca = 2.0f * P12;
+    cb = 2.0f * P22;
+  } else {
+    ca = -2.0f * (P11 + P12);
+    cb = -2.0f * (P12 + P22);
+  }
+  // the other two corners in counter-clockwise order
+  const double3 pb = corner == 0 ? p1 : (corner == 1 ? p2 : p0);
+  const double3 pc = corner == 0 ? p2 : (corner == 1 ? p0 : p1);
+  const float bx = (float)(pb.x - c[0]), by = (float)(pb.y - c[1]), bz = (float)(pb.z - c[2]);
+  const float qx = (float)(pc.x - c[0]), qy = (float)(pc.y - c[1]), qz = (float)(pc.z - c[2]);
+  return make_float3(-(ca * e1[0] + cb * e2[0]) - pv * (by * qz - bz * qy),
+                     -(ca * e1[1] + cb * e2[1]) - pv * (bz * qx - bx * qz),
+                     -(ca * e1[2] + cb * e2[2]) - pv * (bx * qy - by * qx));
 }
 
-// Kantor-Nelson bending force kt sin(theta - theta0) * (-d theta / d x_role) on
-// one vertex of hinge h (x1, x2 shared edge; x3, x4 opposite).  With
+// Kantor-Nelson bending force -kt sin(theta - theta0) d theta / d x_role on one
+// vertex of hinge h (x1, x2 shared edge; x3, x4 opposite).  With
 // nA = (x2-x1) x (x3-x1), nB = (x1-x2) x (x4-x2), e = x2 - x1:
 //   d theta/d x3 = -|e| nA/|nA|^2,  d theta/d x4 = -|e| nB/|nB|^2,
 //   d theta/d x1 = -((x3-x2).e^) nA/|nA|^2 + ((x2-x4).e^) nB/|nB|^2,
 //   d theta/d x2 = -((x1-x3).e^) nA/|nA|^2 + ((x4-x1).e^) nB/|nB|^2.
+// sin(theta - theta0) = sin theta cos theta0 - cos theta sin theta0 with
+// cos theta = nA.nB/(|nA||nB|), sin theta = (nA x nB).e^/(|nA||nB|), in FP64.
 __device__ inline float3 bending_role(const Dev& d, const Bead& Bd, int h, int role) {
   const int nh = d.nh;
   const double3 x1 = load_pos(d.pos, d.nm, d.hinge[h]);
@@ -264,18 +257,19 @@ __device__ inline float3 bending_role(const Dev& d, const Bead& Bd, int h, int r
   const double ex = x2.x - x1.x, ey = x2.y - x1.y, ez = x2.z - x1.z;
   const double ax = x3.x - x1.x, ay = x3.y - x1.y, az = x3.z - x1.z;
   const double bx = x4.x - x2.x, by = x4.y - x2.y, bz = x4.z - x2.z;
-  // nA = e x a ; nB = (-e) x b
   const double nAx = ey * az - ez * ay, nAy = ez * ax - ex * az, nAz = ex * ay - ey * ax;
   const double nBx = -(ey * bz - ez * by), nBy = -(ez * bx - ex * bz), nBz = -(ex * by - ey * bx);
   const double nA2 = nAx * nAx + nAy * nAy + nAz * nAz;
   const double nB2 = nBx * nBx + nBy * nBy + nBz * nBz;
   const double E = sqrt(ex * ex + ey * ey + ez * ez);
-  // signed angle from nA to nB about e
+  const double iE = 1.0 / E;
+  const double ehx = ex * iE, ehy = ey * iE, ehz = ez * iE;
   const double cx = nAy * nBz - nAz * nBy, cy = nAz * nBx - nAx * nBz, cz = nAx * nBy - nAy * nBx;
-  const double th = atan2((cx * ex + cy * ey + cz * ez) / E, nAx * nBx + nAy * nBy + nAz * nBz);
-  const float dW = Bd.kt * (float)sin(th - (double)d.theta0[h]);
-  double ca, cb;  // coefficients of nA/|nA|^2 and nB/|nB|^2 in d theta / d x_role
-  const double ehx = ex / E, ehy = ey / E, ehz = ez / E;
+  const double inorm = 1.0 / sqrt(nA2 * nB2);
+  const double sn = (cx * ehx + cy * ehy + cz * ehz) * inorm;
+  const double cs = (nAx * nBx + nAy * nBy + nAz * nBz) * inorm;
+  const float dW = Bd.kt * (float)(sn * d.th0cs[h] - cs * d.th0cs[nh + h]);
+  double ca, cb;  // d theta / d x_role = ca nA/|nA|^2 + cb nB/|nB|^2
   if (role == 2) {
     ca = -E;
     cb = 0;
@@ -294,42 +288,82 @@ __device__ inline float3 bending_role(const Dev& d, const Bead& Bd, int h, int r
                      -dW * (fa * (float)nAz + fb * (float)nBz));
 }
 
+// Driving + spring force on bead `slot` of swimmer S at step n (Sec. 2.2):
+// f1 = A sin(w n + phi0) x, f3 = B sin(w n + phi0 + alpha) x, f2 = -f1 - f3,
+// springs f_o = -k (|R_o - R_2| - L) (R_o - R_2)/|R_o - R_2| on the outer
+// beads with the opposite force on the middle one.
+__device__ inline void bead_force(const Dev& d, const Swimmer& S, int slot, int64_t n, double* f) {
+  const double t = (double)n;
+  const double f1 = S.A * sin(S.omega * t + S.phi0);
+  const double f3 = S.B * sin(S.omega * t + S.phi0 + S.alpha);
+  f[0] = slot == 0 ? f1 : (slot == 2 ? f3 : -f1 - f3);
+  f[1] = 0;
+  f[2] = 0;
+  const double* R2 = d.bstate[S.bead[1]].c;
+  for (int sp = 0; sp < 2; ++sp) {
+    const int outer = sp == 0 ? 0 : 2;
+    if (slot != outer && slot != 1) continue;
+    const double* Ro = d.bstate[S.bead[outer]].c;
+    const double dx = Ro[0] - R2[0], dy = Ro[1] - R2[1], dz = Ro[2] - R2[2];
+    const double len = sqrt(dx * dx + dy * dy + dz * dz);
+    const double s = (slot == outer ? -1.0 : 1.0) * S.k[sp] * (len - S.L0[sp]) / len;
+    f[0] += s * dx;
+    f[1] += s * dy;
+    f[2] += s * dz;
+  }
+}
+
+// 32 lanes per mesh node: lanes 0..7 take the node's incident triangles
+// (Skalak + volume), lanes 8..31 the hinges it belongs to (its own edges and
+// the edges opposite it: bending); a fixed shuffle tree sums them, and lane 0
+// adds the node's 1/N_v share of the bead force (Sec. 2.2).
+constexpr int kVertLanes = 32;
+constexpr int kVertTriLanes = 8;
 __global__ __launch_bounds__(256) void k_vertex_forces(Dev d) {
-  const int m = blockIdx.x * 256 + threadIdx.x;
-  if (m >= d.nm) return;
-  const int b = d.marker_bead[m];
-  const Bead Bd = d.beads[b];
-  const BeadState st = d.bstate[b];
+  const int gid = blockIdx.x * 256 + threadIdx.x;
+  const int m = gid / kVertLanes, lane = gid % kVertLanes;
   float fx = 0, fy = 0, fz = 0;
-  // volume penalty: f = -kv (V - V0)/V0 dV/dr, dV/dr = 1/6 sum (r_b - c) x (r_c - c)
-  const float pref = (float)(Bd.kv * (st.V - Bd.V0) / Bd.V0) * (1.0f / 6.0f);
-  for (int k = d.vt_off[m]; k < d.vt_off[m + 1]; ++k) {
-    const int e = d.vt[k];
-    const int t = e / 3, corner = e % 3;
-    const float3 f = skalak_corner(d, Bd, t, corner);
-    fx += f.x;
-    fy += f.y;
-    fz += f.z;
-    const int jb = d.tri[((corner + 1) % 3) * d.ntri + t];
-    const int jc = d.tri[((corner + 2) % 3) * d.ntri + t];
-    const double3 pb = load_pos(d.pos, d.nm, jb), pc = load_pos(d.pos, d.nm, jc);
-    const float bx = (float)(pb.x - st.c[0]), by = (float)(pb.y - st.c[1]), bz = (float)(pb.z - st.c[2]);
-    const float cx = (float)(pc.x - st.c[0]), cy = (float)(pc.y - st.c[1]), cz = (float)(pc.z - st.c[2]);
-    fx -= pref * (by * cz - bz * cy);
-    fy -= pref * (bz * cx - bx * cz);
-    fz -= pref * (bx * cy - by * cx);
+  int b = 0;
+  if (m < d.nm) {
+    b = d.marker_bead[m];
+    const Bead Bd = d.beads[b];
+    const BeadState& st = d.bstate[b];
+    if (lane < kVertTriLanes) {
+      const int k = d.vt_off[m] + lane;
+      if (k < d.vt_off[m + 1]) {
+        const int e = d.vt[k];
+        const float pv = (float)(Bd.kv * (st.V - Bd.V0) / (6.0 * Bd.V0));
+        const float3 f = triangle_corner(d, Bd, e / 3, e % 3, st.c, pv);
+        fx = f.x;
+        fy = f.y;
+        fz = f.z;
+      }
+    } else {
+      const int k = d.vh_off[m] + lane - kVertTriLanes;
+      if (k < d.vh_off[m + 1]) {
+        const int e = d.vh[k];
+        const float3 f = bending_role(d, Bd, e / 4, e % 4);
+        fx = f.x;
+        fy = f.y;
+        fz = f.z;
+      }
+    }
   }
-  for (int k = d.vh_off[m]; k < d.vh_off[m + 1]; ++k) {
-    const int e = d.vh[k];
-    const float3 f = bending_role(d, Bd, e / 4, e % 4);
-    fx += f.x;
-    fy += f.y;
-    fz += f.z;
+#pragma unroll
+  for (int s = kVertLanes / 2; s > 0; s >>= 1) {
+    fx += __shfl_xor(fx, s, 64);
+    fy += __shfl_xor(fy, s, 64);
+    fz += __shfl_xor(fz, s, 64);
   }
-  const float inv = 1.0f / (float)Bd.nv;
-  d.fm[m] = fx + (float)st.fb[0] * inv;
-  d.fm[d.nm + m] = fy + (float)st.fb[1] * inv;
-  d.fm[2 * d.nm + m] = fz + (float)st.fb[2] * inv;
+  if (m < d.nm && lane == 0) {
+    const Bead Bd = d.beads[b];
+    double fb[3];
+    bead_force(d, d.swimmers[Bd.swimmer], Bd.slot, *d.step, fb);
+    const float inv = 1.0f / (float)Bd.nv;
+    d.fm[m] = fx + (float)fb[0] * inv;
+    d.fm[d.nm + m] = fy + (float)fb[1] * inv;
+    d.fm[2 * d.nm + m] = fz + (float)fb[2] * inv;
+  }
 }
 
 // ---- spreading --------------------------------------------------------------------
@@ -354,16 +388,26 @@ __device__ inline bool stencil_offset(int base, int origin, int extent, int N, i
   return false;
 }
 
+// One workgroup per tile.  The markers whose stencils meet the tile are
+// compacted in (bead, marker) order; the thread that finds a marker stages its
+// stencil offset, its per-axis kernel weights and its force in LDS.  Entry e
+// goes to wavefront e % 8, which adds the marker's stencil (one lane per
+// stencil node, all distinct) into the wavefront's private LDS copy of the
+// tile; the eight copies are summed in wavefront order.  No atomics, fixed
+// summation order: deterministic.
+constexpr int kSpreadWaves = kSpreadBlock / 64;
+template <int NW>
 struct SpreadEntry {
-  int ox, oy, oz;
-  float wx[4], wy[4], wz[4];
-  float f[3];
+  int off;           // packed stencil offset from the tile origin, +8 per axis
+  float w[3][NW];    // per-axis kernel weights of the stencil nodes
+  float f[3];        // marker force
 };
 
 template <int NW>
 __global__ __launch_bounds__(kSpreadBlock) void k_spread(Dev d) {
-  __shared__ SpreadEntry ent[kSpreadBlock];
-  __shared__ int wave_cnt[kSpreadBlock / 64];
+  __shared__ float acc[kSpreadWaves][3][kSpreadBlock];
+  __shared__ SpreadEntry<NW> ent[kSpreadBlock];
+  __shared__ int wave_cnt[kSpreadWaves];
   const int blk = blockIdx.x;
   const int b = d.spread_bead[blk];
   const Bead Bd = d.beads[b];
@@ -378,9 +422,14 @@ __global__ __launch_bounds__(kSpreadBlock) void k_spread(Dev d) {
   const int64_t n = *d.step;
   const int ox = tx * kTile, oy = ty * kTile, oz = tz * kTile;
   const int ex = min(kTile, B.nx - ox), ey = min(kTile, B.ny - oy), ez = min(kTile, B.nz - oz);
-  const int lx = threadIdx.x % kTile, ly = (threadIdx.x / kTile) % kTile, lz = threadIdx.x / (kTile * kTile);
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
-  float ax = 0, ay = 0, az = 0;
+  for (int w = 0; w < kSpreadWaves; ++w) {
+    acc[w][0][threadIdx.x] = 0.0f;
+    acc[w][1][threadIdx.x] = 0.0f;
+    acc[w][2][threadIdx.x] = 0.0f;
+  }
+  // stencil node of this lane (NW^3 <= 64 lanes used)
+  const int sa = lane % NW, sb = (lane / NW) % NW, sc = lane / (NW * NW);
   for (int b2 = b; b2 < B.bead0 + B.nbeads; ++b2) {
     if (b2 != b && !covers(d.bstate[b2], tx, ty, tz, B)) continue;
     const Bead Q = d.beads[b2];
@@ -389,33 +438,33 @@ __global__ __launch_bounds__(kSpreadBlock) void k_spread(Dev d) {
       bool take = false;
       int offx = 0, offy = 0, offz = 0;
       double3 p = make_double3(0, 0, 0);
+      int bx = 0, by = 0, bz = 0;
       if (i < Q.nv) {
         p = load_pos(d.pos, d.nm, Q.first + i);
-        take = stencil_offset<NW>(stencil_base<NW>(p.x), ox, ex, B.nx, offx) &&
-               stencil_offset<NW>(stencil_base<NW>(p.y), oy, ey, B.ny, offy) &&
-               stencil_offset<NW>(stencil_base<NW>(p.z), oz, ez, B.nz, offz);
+        bx = stencil_base<NW>(p.x);
+        by = stencil_base<NW>(p.y);
+        bz = stencil_base<NW>(p.z);
+        take = stencil_offset<NW>(bx, ox, ex, B.nx, offx) && stencil_offset<NW>(by, oy, ey, B.ny, offy) &&
+               stencil_offset<NW>(bz, oz, ez, B.nz, offz);
       }
-      // deterministic compaction: slot = markers taken before this one
       const unsigned long long mask = __ballot(take);
       const int before = __popcll(mask & ((1ull << lane) - 1ull));
+      __syncthreads();  // previous chunk's entries fully consumed
       if (lane == 0) wave_cnt[wave] = __popcll(mask);
       __syncthreads();
       int slot = before, total = 0;
-      for (int w = 0; w < kSpreadBlock / 64; ++w) {
+      for (int w = 0; w < kSpreadWaves; ++w) {
         if (w < wave) slot += wave_cnt[w];
         total += wave_cnt[w];
       }
       if (take) {
-        SpreadEntry& E = ent[slot];
-        E.ox = offx;
-        E.oy = offy;
-        E.oz = offz;
-        const int bx = stencil_base<NW>(p.x), by = stencil_base<NW>(p.y), bz = stencil_base<NW>(p.z);
+        SpreadEntry<NW>& E = ent[slot];
+        E.off = ((offx + 8) << 10) | ((offy + 8) << 5) | (offz + 8);
 #pragma unroll
         for (int a = 0; a < NW; ++a) {
-          E.wx[a] = phi<NW>((float)((double)(bx + a) - p.x));
-          E.wy[a] = phi<NW>((float)((double)(by + a) - p.y));
-          E.wz[a] = phi<NW>((float)((double)(bz + a) - p.z));
+          E.w[0][a] = phi<NW>((float)((double)(bx + a) - p.x));
+          E.w[1][a] = phi<NW>((float)((double)(by + a) - p.y));
+          E.w[2][a] = phi<NW>((float)((double)(bz + a) - p.z));
         }
         const int m = Q.first + i;
         E.f[0] = d.fm[m];
@@ -423,19 +472,32 @@ __global__ __launch_bounds__(kSpreadBlock) void k_spread(Dev d) {
         E.f[2] = d.fm[2 * d.nm + m];
       }
       __syncthreads();
-      for (int e = 0; e < total; ++e) {
-        const int ix = lx - ent[e].ox, iy = ly - ent[e].oy, iz = lz - ent[e].oz;
-        if ((unsigned)ix < (unsigned)NW && (unsigned)iy < (unsigned)NW && (unsigned)iz < (unsigned)NW) {
-          const float w = ent[e].wx[ix] * ent[e].wy[iy] * ent[e].wz[iz];
-          ax += w * ent[e].f[0];
-          ay += w * ent[e].f[1];
-          az += w * ent[e].f[2];
+      if (lane < NW * NW * NW) {
+        for (int e = wave; e < total; e += kSpreadWaves) {
+          const SpreadEntry<NW>& E = ent[e];
+          const int lx = ((E.off >> 10) & 31) - 8 + sa;
+          const int ly = ((E.off >> 5) & 31) - 8 + sb;
+          const int lz = (E.off & 31) - 8 + sc;
+          if ((unsigned)lx < (unsigned)ex && (unsigned)ly < (unsigned)ey && (unsigned)lz < (unsigned)ez) {
+            const float w = E.w[0][sa] * E.w[1][sb] * E.w[2][sc];
+            const int node = lx + kTile * (ly + kTile * lz);
+            acc[wave][0][node] += w * E.f[0];
+            acc[wave][1][node] += w * E.f[1];
+            acc[wave][2][node] += w * E.f[2];
+          }
         }
       }
-      __syncthreads();
     }
   }
+  __syncthreads();
+  const int lx = threadIdx.x % kTile, ly = (threadIdx.x / kTile) % kTile, lz = threadIdx.x / (kTile * kTile);
   if (lx < ex && ly < ey && lz < ez) {
+    float ax = 0, ay = 0, az = 0;
+    for (int w = 0; w < kSpreadWaves; ++w) {
+      ax += acc[w][0][threadIdx.x];
+      ay += acc[w][1][threadIdx.x];
+      az += acc[w][2][threadIdx.x];
+    }
     const int64_t node = B.node0 + (int64_t)(oz + lz) * B.nx * B.ny + (int64_t)(oy + ly) * B.nx + (ox + lx);
     d.F[node] = ax;
     d.F[d.pstride + node] = ay;
@@ -501,13 +563,14 @@ __global__ __launch_bounds__(kStatsBlock) void k_bead_centres(Dev d, double* out
 }  // namespace
 
 void launch_bead_stats(const Dev& d, hipStream_t s) {
-  if (d.width == 2) hipLaunchKernelGGL(k_bead_stats<2>, dim3(d.nswimmers), dim3(kStatsBlock), 0, s, d);
-  else if (d.width == 3) hipLaunchKernelGGL(k_bead_stats<3>, dim3(d.nswimmers), dim3(kStatsBlock), 0, s, d);
-  else hipLaunchKernelGGL(k_bead_stats<4>, dim3(d.nswimmers), dim3(kStatsBlock), 0, s, d);
+  if (d.width == 2) hipLaunchKernelGGL(k_bead_stats<2>, dim3(d.nbeads), dim3(kStatsBlock), 0, s, d);
+  else if (d.width == 3) hipLaunchKernelGGL(k_bead_stats<3>, dim3(d.nbeads), dim3(kStatsBlock), 0, s, d);
+  else hipLaunchKernelGGL(k_bead_stats<4>, dim3(d.nbeads), dim3(kStatsBlock), 0, s, d);
 }
 
 void launch_vertex_forces(const Dev& d, hipStream_t s) {
-  hipLaunchKernelGGL(k_vertex_forces, dim3((d.nm + 255) / 256), dim3(256), 0, s, d);
+  const int blocks = (int)(((int64_t)d.nm * kVertLanes + 255) / 256);
+  hipLaunchKernelGGL(k_vertex_forces, dim3(blocks), dim3(256), 0, s, d);
 }
 
 void launch_spread(const Dev& d, hipStream_t s) {

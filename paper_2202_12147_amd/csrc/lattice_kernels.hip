@@ -19,6 +19,8 @@
 
 #include "common.h"
 
+#include <algorithm>
+
 namespace lbmib {
 
 namespace {
@@ -112,16 +114,27 @@ __device__ inline void collide_pair(float& gp, float& gm, float w, float om, flo
   gm = gm + om * (eqm - gm) + (s_sym - s_asym);
 }
 
-template <int ST>
-__global__ __launch_bounds__(kScBlock) void k_stream_collide(Dev d, int tick) {
+// Workgroup -> logical block.  Workgroups are handed to the 8 XCDs round
+// robin; with `remap` each XCD instead receives one contiguous range of
+// logical blocks, so the cache lines shared by neighbouring blocks (the
+// x-shifted pulls straddle block edges) stay in one XCD's L2.
+__device__ inline int logical_block(int remap, int nblocks) {
+  if (!remap) return blockIdx.x;
+  const int per = (int)gridDim.x / 8;  // grid is a multiple of 8 when remapping
+  return (blockIdx.x % 8) * per + blockIdx.x / 8;
+}
+
+template <int ST, int BS>
+__global__ __launch_bounds__(BS) void k_stream_collide(Dev d, int tick, int remap, int nblocks) {
   using IO = PopIO<ST>;
   using T = typename IO::T;
-  const int blk = blockIdx.x;
-  const int b = d.nboxes == 1 ? 0 : d.block_box[blk];
-  const Box B = d.boxes[b];
+  const int blk = logical_block(remap, nblocks);
   const int64_t n = *d.step;
-  const int id = (blk - B.block0) * kScBlock + (int)threadIdx.x;
-  if (id < B.n) {
+  const int b = (d.nboxes == 1 || blk >= nblocks) ? 0 : d.sc_block_box[blk];
+  const Box B = d.boxes[b];
+  const int first = d.nboxes == 1 ? 0 : d.sc_box_block0[b];
+  const int id = (blk - first) * BS + (int)threadIdx.x;
+  if (blk < nblocks && id < B.n) {
     const int nx = B.nx, ny = B.ny, nz = B.nz;
     const int x = id % nx;
     const int yz = id / nx;
@@ -314,13 +327,41 @@ __global__ __launch_bounds__(kScBlock) void k_conserved_final(const double* __re
     for (int k = 0; k < 4; ++k) out[k] = v[k];
 }
 
+// Plain device copy (16 bytes per thread per iteration, grid-stride): the
+// achievable-bandwidth reference for the HBM roofline.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void k_copy(const f32x4* __restrict__ src, f32x4* __restrict__ dst,
+                                              int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    __builtin_nontemporal_store(src[i], dst + i);
+}
+
 }  // namespace
 
-void launch_stream_collide(const Dev& d, int storage, int nblocks, int tick, hipStream_t s) {
-  if (storage == kFp16)
-    hipLaunchKernelGGL(k_stream_collide<kFp16>, dim3(nblocks), dim3(kScBlock), 0, s, d, tick);
+void launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t s) {
+  const int64_t n = bytes / 16;
+  const int blocks = (int)std::min<int64_t>((n + 255) / 256, 256 * 64);
+  hipLaunchKernelGGL(k_copy, dim3(blocks), dim3(256), 0, s, static_cast<const f32x4*>(src),
+                     static_cast<f32x4*>(dst), n);
+}
+
+template <int ST>
+static void launch_sc_st(const Dev& d, int block, int nblocks, int tick, int remap, hipStream_t s) {
+  const int grid = remap ? (nblocks + 7) / 8 * 8 : nblocks;
+  if (block == 128)
+    hipLaunchKernelGGL((k_stream_collide<ST, 128>), dim3(grid), dim3(128), 0, s, d, tick, remap, nblocks);
+  else if (block == 512)
+    hipLaunchKernelGGL((k_stream_collide<ST, 512>), dim3(grid), dim3(512), 0, s, d, tick, remap, nblocks);
   else
-    hipLaunchKernelGGL(k_stream_collide<kFp32>, dim3(nblocks), dim3(kScBlock), 0, s, d, tick);
+    hipLaunchKernelGGL((k_stream_collide<ST, 256>), dim3(grid), dim3(256), 0, s, d, tick, remap, nblocks);
+}
+
+void launch_stream_collide(const Dev& d, int storage, int block, int nblocks, int tick, int remap,
+                           hipStream_t s) {
+  if (storage == kFp16)
+    launch_sc_st<kFp16>(d, block, nblocks, tick, remap, s);
+  else
+    launch_sc_st<kFp32>(d, block, nblocks, tick, remap, s);
 }
 
 void launch_tick(const Dev& d, hipStream_t s) {

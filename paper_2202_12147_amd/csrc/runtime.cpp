@@ -136,7 +136,8 @@ struct lbm_handle {
   std::vector<int> hinge;    // [nh][4]
   int nm = 0;
   int64_t nodes = 0, pstride = 0;
-  int ntiles = 0, sc_blocks = 0, spread_blocks = 0;
+  int ntiles = 0, sc_blocks = 0, spread_blocks = 0, out_blocks = 0;
+  int sc_block = 256, sc_remap = 1;  // stream-collide launch shape
   bool uploaded = false, stepped = false;
   int64_t host_step = 0;  // steps enqueued
 
@@ -232,6 +233,9 @@ int upload(lbm_handle* h) {
     }
   std::vector<int> vt_off(nm + 1, 0), vh_off(nm + 1, 0), vtf, vhf;
   for (int m = 0; m < nm; ++m) {
+    // the node-force kernel gives each node 8 triangle and 24 hinge lanes
+    if (vt[m].size() > 8 || vh[m].size() > 24)
+      return h->fail(LBM_EINVAL, "mesh node with more than 8 triangles or 24 hinges");
     vt_off[m + 1] = vt_off[m] + (int)vt[m].size();
     vh_off[m + 1] = vh_off[m] + (int)vh[m].size();
     vtf.insert(vtf.end(), vt[m].begin(), vt[m].end());
@@ -269,7 +273,7 @@ int upload(lbm_handle* h) {
   h->d_A0 = h->alloc<float>(A0.size(), rc);
   h->d_idet = h->alloc<float>(idet.size(), rc);
   h->d_hinge = h->alloc<int>(hinge.size(), rc);
-  h->d_theta0 = h->alloc<double>(h->hingeth0.size(), rc);
+  h->d_theta0 = h->alloc<double>(2 * h->hingeth0.size(), rc);
   h->d_vt_off = h->alloc<int>(vt_off.size(), rc);
   h->d_vt = h->alloc<int>(vtf.size(), rc);
   h->d_vh_off = h->alloc<int>(vh_off.size(), rc);
@@ -292,7 +296,14 @@ int upload(lbm_handle* h) {
   put(h->d_A0, A0.data(), sizeof(float) * A0.size());
   put(h->d_idet, idet.data(), sizeof(float) * idet.size());
   put(h->d_hinge, hinge.data(), sizeof(int) * hinge.size());
-  put(h->d_theta0, h->hingeth0.data(), sizeof(double) * h->hingeth0.size());
+  {
+    std::vector<double> cs(2 * (size_t)nh);
+    for (int e = 0; e < nh; ++e) {
+      cs[e] = std::cos(h->hingeth0[e]);
+      cs[nh + e] = std::sin(h->hingeth0[e]);
+    }
+    put(h->d_theta0, cs.data(), sizeof(double) * cs.size());
+  }
   put(h->d_vt_off, vt_off.data(), sizeof(int) * vt_off.size());
   put(h->d_vt, vtf.data(), sizeof(int) * vtf.size());
   put(h->d_vh_off, vh_off.data(), sizeof(int) * vh_off.size());
@@ -317,7 +328,7 @@ int upload(lbm_handle* h) {
   d.A0 = h->d_A0;
   d.idetG0 = h->d_idet;
   d.hinge = h->d_hinge;
-  d.theta0 = h->d_theta0;
+  d.th0cs = h->d_theta0;
   d.ntri = ntri;
   d.nh = nh;
   d.vt_off = h->d_vt_off;
@@ -351,7 +362,7 @@ void enqueue_step(lbm_handle* h) {
     }
     (void)hipEventRecord(h->ev_pool[h->ev_used++], h->stream);
   }
-  launch_stream_collide(d, h->storage, h->sc_blocks, ibm ? 0 : 1, h->stream);
+  launch_stream_collide(d, h->storage, h->sc_block, h->sc_blocks, ibm ? 0 : 1, h->sc_remap, h->stream);
   if (h->timing) (void)hipEventRecord(h->ev_pool[h->ev_used++], h->stream);
   if (ibm) launch_interp_advance(d, h->stream);
 }
@@ -464,7 +475,8 @@ int lbm_create(const lbm_grid* grid, double tau, int forcing, const lbm_opts* op
   h->nodes = B.n;
   h->pstride = (B.n + 127) / 128 * 128;
   h->ntiles = B.tx * B.ty * B.tz;
-  h->sc_blocks = (int)((B.n + kScBlock - 1) / kScBlock);
+  h->out_blocks = (int)((B.n + kScBlock - 1) / kScBlock);
+  h->sc_blocks = (int)((B.n + h->sc_block - 1) / h->sc_block);
 
   const size_t eb = element_bytes(h);
   h->pop[0] = h->alloc<char>(eb * kQ * h->pstride, rc);
@@ -771,7 +783,7 @@ static int get_macro(lbm_handle* h, float* dst, int on_device, bool vel) {
     }
     target = h->uout;
   }
-  launch_velocity(h->dev, h->storage, h->sc_blocks, vel ? target : nullptr, vel ? nullptr : target,
+  launch_velocity(h->dev, h->storage, h->out_blocks, vel ? target : nullptr, vel ? nullptr : target,
                   h->stream);
   rc = h->hip(hipGetLastError(), "k_velocity launch");
   if (rc) return rc;
@@ -918,6 +930,52 @@ int lbm_kernel_time(lbm_handle* h, double* ms, int64_t* launches) {
   harvest_timing(h);
   if (ms) *ms = h->timed_ms;
   if (launches) *launches = h->timed_launches;
+  return LBM_OK;
+}
+
+int lbm_probe_copy_bandwidth(int64_t bytes, int iters, double* gbs) {
+  if (bytes < 16 * 1024 || iters < 1 || !gbs) return LBM_EINVAL;
+  bytes = bytes / 16 * 16;
+  void *a = nullptr, *b = nullptr;
+  hipStream_t s = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = LBM_OK;
+  if (hipMalloc(&a, bytes) != hipSuccess || hipMalloc(&b, bytes) != hipSuccess) rc = LBM_ENOMEM;
+  if (!rc && (hipStreamCreate(&s) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+              hipEventCreate(&e1) != hipSuccess))
+    rc = LBM_EDEVICE;
+  if (!rc && hipMemsetAsync(a, 0, bytes, s) != hipSuccess) rc = LBM_EDEVICE;
+  if (!rc) {
+    launch_copy(a, b, bytes, s);  // warm up
+    (void)hipEventRecord(e0, s);
+    for (int i = 0; i < iters; ++i) launch_copy(i & 1 ? b : a, i & 1 ? a : b, bytes, s);
+    (void)hipEventRecord(e1, s);
+    if (hipEventSynchronize(e1) != hipSuccess) rc = LBM_EDEVICE;
+  }
+  if (!rc) {
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    *gbs = 2.0 * (double)bytes * iters / (ms * 1e-3) / 1e9;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (s) (void)hipStreamDestroy(s);
+  if (a) (void)hipFree(a);
+  if (b) (void)hipFree(b);
+  return rc;
+}
+
+int lbm_set_stream_collide_launch(lbm_handle* h, int block, int xcd_remap) {
+  if (!h || (block != 128 && block != 256 && block != 512)) return LBM_EINVAL;
+  if (h->boxes.size() != 1) return h->fail(LBM_ESTATE, "launch shape of a batch is set by its tuner");
+  int rc = h->hip(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+  if (rc) return rc;
+  h->sc_block = block;
+  h->sc_remap = xcd_remap ? 1 : 0;
+  h->sc_blocks = (int)((h->nodes + block - 1) / block);
+  if (h->g_chunk) (void)hipGraphExecDestroy(h->g_chunk);
+  if (h->g_one) (void)hipGraphExecDestroy(h->g_one);
+  h->g_chunk = h->g_one = nullptr;
   return LBM_OK;
 }
 

@@ -27,6 +27,7 @@ SYMBOLS = [
     "lbm_get_marker_forces", "lbm_get_velocity",
     "lbm_get_density", "lbm_get_conserved", "lbm_set_populations", "lbm_get_populations",
     "lbm_save", "lbm_load", "lbm_set_kernel_timing", "lbm_kernel_time", "lbm_bytes_per_step",
+    "lbm_probe_copy_bandwidth", "lbm_set_stream_collide_launch",
     "lbm_strerror", "lbm_last_error",
 ]
 
@@ -108,6 +109,8 @@ def load_library():
         "lbm_set_kernel_timing": (C.c_int, [vp, C.c_int]),
         "lbm_kernel_time": (C.c_int, [vp, C.POINTER(C.c_double), C.POINTER(i64)]),
         "lbm_bytes_per_step": (i64, [vp]),
+        "lbm_probe_copy_bandwidth": (C.c_int, [i64, C.c_int, C.POINTER(C.c_double)]),
+        "lbm_set_stream_collide_launch": (C.c_int, [vp, C.c_int, C.c_int]),
         "lbm_strerror": (C.c_char_p, [C.c_int]),
         "lbm_last_error": (C.c_char_p, [vp]),
     }
@@ -299,9 +302,22 @@ class Lattice:
         self._check(self.lib.lbm_kernel_time(self.h, C.byref(ms), C.byref(n)))
         return ms.value, n.value
 
+    def set_stream_collide_launch(self, block=256, xcd_remap=False):
+        self._check(self.lib.lbm_set_stream_collide_launch(self.h, int(block), int(bool(xcd_remap))))
+
     @property
     def bytes_per_step(self):
         return self.lib.lbm_bytes_per_step(self.h)
+
+
+def copy_bandwidth(nbytes=1 << 30, iters=20):
+    """Achievable device-memory bandwidth (GB/s, read + write) of a plain copy."""
+    lib = load_library()
+    out = C.c_double()
+    rc = lib.lbm_probe_copy_bandwidth(int(nbytes), int(iters), C.byref(out))
+    if rc:
+        raise LbmError(rc, lib.lbm_strerror(rc).decode())
+    return out.value
 
 
 def from_workload(case, storage=FP32_SHIFTED, fp16_scale=1.0, use_graphs=True, stream=None):

@@ -123,3 +123,22 @@ def test_shear_wave_viscosity_on_gpu():
     a1 = (lat.velocity()[0][0, :, 0].astype(np.float64) * s).sum()
     nu = -np.log(a1 / a0) / ((2 * np.pi / N) ** 2 * 256)
     assert abs(nu / ((tau - 0.5) / 3) - 1) < 3e-3
+
+
+@pytest.mark.parametrize("block,remap", [(128, 0), (512, 1), (256, 1)])
+def test_launch_shapes_bitwise_equal(block, remap):
+    shape = (40, 24, 33)
+    dev = wl.random_deviation(shape, 6, 1e-4)
+    a = lbmib.Lattice(shape, 0.9, use_graphs=False)
+    b = lbmib.Lattice(shape, 0.9)
+    b.set_stream_collide_launch(block, remap)
+    for x in (a, b):
+        x.set_populations(dev)
+        x.set_body_force((1e-6, 2e-6, 0))
+        x.step(9)
+    assert np.array_equal(a.populations(), b.populations())
+
+
+def test_copy_probe_reports_bandwidth():
+    gbs = lbmib.copy_bandwidth(1 << 28, 10)
+    assert 500 < gbs < 20000
