@@ -102,7 +102,8 @@ def main():
                    "storage": "fp32 shifted"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
-                     "kernel": "k_stream_collide<fp32>", "avg_kernel_ms": round(avg_ms, 5),
+                     "kernel": "k_stream_collide<fp32> (bulk + near-block launches per step)",
+                     "avg_kernel_ms": round(avg_ms, 5),
                      "bytes_per_launch": lat.bytes_per_step},
     }
     if not args.no_cpu:

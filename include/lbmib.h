@@ -192,10 +192,14 @@ int lbm_load(lbm_handle* h, const char* path);
 int lbm_set_kernel_timing(lbm_handle* h, int on);
 int lbm_kernel_time(lbm_handle* h, double* ms, int64_t* launches);
 /* Launch shape of the stream-collide kernel: workgroup size 128, 256 or 512
- * nodes, and whether workgroups are remapped so that each of the 8 XCDs
- * streams one contiguous range of the grid.  Results are bitwise identical
- * for every shape.  Errors: LBM_EINVAL. */
-int lbm_set_stream_collide_launch(lbm_handle* h, int block, int xcd_remap);
+ * nodes; whether workgroups are remapped so that each of the 8 XCDs streams
+ * one contiguous range of the grid; and, with swimmers, `resident` > 0 makes
+ * the launch that runs concurrently with the immersed-boundary kernels
+ * persistent with that many workgroups per compute unit (0: one workgroup
+ * per block; -1: no concurrency, the immersed-boundary kernels then one
+ * full-grid launch).  Results are bitwise identical for every shape.
+ * Errors: LBM_EINVAL. */
+int lbm_set_stream_collide_launch(lbm_handle* h, int block, int xcd_remap, int resident);
 /* Algorithmic bytes one stream-collide launch moves (19 populations read and
  * written once per node at the storage width). */
 int64_t lbm_bytes_per_step(const lbm_handle* h);

@@ -22,6 +22,7 @@ constexpr int kScBlock = 256;  // stream-collide threads per block
 
 enum Forcing { kGuo = 0, kShanChen = 1 };
 enum Storage { kFp32 = 0, kFp16 = 1 };
+enum ScLaunch { kLaunchAll = 0, kLaunchBulk = 1, kLaunchActive = 2 };
 
 // One periodic box.  A single-box handle has exactly one.
 struct Box {
@@ -77,8 +78,8 @@ struct Dev {
   const int* block_box;  // 256-node block -> box (output and reduction kernels)
   const int* sc_block_box;   // stream-collide block -> box (tuned block size)
   const int* sc_box_block0;  // first stream-collide block of each box
-  int64_t* step;         // device step counter
-  unsigned* done;        // last-block counter for the step tick
+  int64_t* step;         // device step counter: first step of the enqueued chunk
+  int sub;               // offset of this launch's step within the chunk
   float fp16_scale, fp16_inv;
   // markers and meshes
   double* pos;           // [3][nm]
@@ -108,20 +109,29 @@ struct Dev {
   const int* vt;
   const int* vh_off;
   const int* vh;
+  // stream-collide blocks near the swimmers: flags near[parity][block] = step
+  // that marked the block, and per-parity block lists (near_list[parity][i],
+  // near_count[parity]); a block is near when it holds a node within two
+  // nodes of a bead's stencil region
+  int* near;
+  int* near_list;
+  int* near_count;
+  int max_near, nsc, sc_bs;
+  const int* tile_box;   // tile -> box (batches only)
   int* overflow;         // set when a bead region outgrows its reserved tiles
   int spread_blocks;
   const int* spread_bead;  // spread block -> bead
 };
 
 // Launch wrappers (defined in the .hip files).
-void launch_stream_collide(const Dev& d, int storage, int block, int nblocks, int tick, int remap,
-                           hipStream_t s);
-void launch_tick(const Dev& d, hipStream_t s);
+void launch_stream_collide(const Dev& d, int storage, int mode, int block, int nblocks, int remap,
+                           int resident, int ncu, hipStream_t s);
+void launch_tick(const Dev& d, int count, hipStream_t s);
 void launch_velocity(const Dev& d, int storage, int nblocks, float* u_out, float* rho_out,
                      hipStream_t s);
 void launch_conserved(const Dev& d, int storage, double* partial, int nparts, double* out,
                       hipStream_t s);
-void launch_bead_stats(const Dev& d, hipStream_t s);
+void launch_bead_stats(const Dev& d, int mark_offset, hipStream_t s);
 void launch_vertex_forces(const Dev& d, hipStream_t s);
 void launch_spread(const Dev& d, hipStream_t s);
 void launch_interp_advance(const Dev& d, hipStream_t s);

@@ -93,11 +93,45 @@ __device__ inline double block_sum(double v, double* sh) {
 // One workgroup per bead: centre (mean of nodes), bounding box and enclosed
 // volume, reduced in FP64 with wavefront shuffles, and from the box the node
 // region the bead's stencils can touch (in 8^3 tiles).
+// Mark the stream-collide blocks holding any node of [lo - 2, hi + 2] (per
+// axis, periodic) as near at step v, listing each newly marked block once.
+__device__ inline void mark_near_blocks(const Dev& d, const Box& B, int box, const int* lo, const int* hi,
+                                        int64_t v) {
+  const int p = (int)(v & 1);
+  const int first = d.nboxes == 1 ? 0 : d.sc_box_block0[box];
+  const int x0 = lo[0] - 2, nxs = hi[0] - lo[0] + 5;
+  const int ny_r = min(hi[1] - lo[1] + 5, B.ny), nz_r = min(hi[2] - lo[2] + 5, B.nz);
+  for (int r = threadIdx.x; r < ny_r * nz_r; r += blockDim.x) {
+    const int y = pmod(lo[1] - 2 + r % ny_r, B.ny), z = pmod(lo[2] - 2 + r / ny_r, B.nz);
+    const int row = (z * B.ny + y) * B.nx;  // box-local id of node (0, y, z)
+    int seg[2][2] = {{0, B.nx - 1}, {0, -1}};
+    if (nxs < B.nx) {
+      const int xs = pmod(x0, B.nx), xe = xs + nxs - 1;
+      seg[0][0] = xs;
+      seg[0][1] = min(xe, B.nx - 1);
+      if (xe >= B.nx) seg[1][1] = xe - B.nx;
+    }
+    for (int sgi = 0; sgi < 2; ++sgi) {
+      if (seg[sgi][1] < seg[sgi][0]) continue;
+      for (int blk = first + (row + seg[sgi][0]) / d.sc_bs; blk <= first + (row + seg[sgi][1]) / d.sc_bs; ++blk) {
+        if (atomicExch(&d.near[p * d.nsc + blk], (int)v) != (int)v) {
+          const int i = atomicAdd(&d.near_count[p], 1);
+          if (i < d.max_near)
+            d.near_list[p * d.max_near + i] = blk;
+          else
+            atomicOr(d.overflow, 2);
+        }
+      }
+    }
+  }
+}
+
 template <int NW>
-__global__ __launch_bounds__(kStatsBlock) void k_bead_stats(Dev d) {
+__global__ __launch_bounds__(kStatsBlock) void k_bead_stats(Dev d, int mark_offset) {
   constexpr int NWAVE = kStatsBlock / 64;
   __shared__ double part[NWAVE][9];
   __shared__ double cen[3];
+  __shared__ int reg_lo[3], reg_hi[3];
   const int b = blockIdx.x;
   const Bead Bd = d.beads[b];
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
@@ -181,8 +215,13 @@ __global__ __launch_bounds__(kStatsBlock) void k_bead_stats(Dev d) {
       if (cnt < 0) cnt = 0;
       st.tlo[a] = t0;
       st.tcnt[a] = cnt;
+      reg_lo[a] = st.lo[a];
+      reg_hi[a] = st.hi[a];
     }
   }
+  __syncthreads();
+  // blocks the next step's stream-collide must treat as near this bead
+  mark_near_blocks(d, d.boxes[Bd.box], Bd.box, reg_lo, reg_hi, *d.step + d.sub + mark_offset);
 }
 
 // ---- membrane forces ------------------------------------------------------------
@@ -358,7 +397,7 @@ __global__ __launch_bounds__(256) void k_vertex_forces(Dev d) {
   if (m < d.nm && lane == 0) {
     const Bead Bd = d.beads[b];
     double fb[3];
-    bead_force(d, d.swimmers[Bd.swimmer], Bd.slot, *d.step, fb);
+    bead_force(d, d.swimmers[Bd.swimmer], Bd.slot, *d.step + d.sub, fb);
     const float inv = 1.0f / (float)Bd.nv;
     d.fm[m] = fx + (float)fb[0] * inv;
     d.fm[d.nm + m] = fy + (float)fb[1] * inv;
@@ -419,7 +458,7 @@ __global__ __launch_bounds__(kSpreadBlock) void k_spread(Dev d) {
   const int tx = pmod(S.tlo[0] + kx, B.tx), ty = pmod(S.tlo[1] + ky, B.ty), tz = pmod(S.tlo[2] + kz, B.tz);
   for (int b2 = B.bead0; b2 < b; ++b2)
     if (covers(d.bstate[b2], tx, ty, tz, B)) return;  // an earlier bead owns this tile
-  const int64_t n = *d.step;
+  const int64_t n = *d.step + d.sub;
   const int ox = tx * kTile, oy = ty * kTile, oz = tz * kTile;
   const int ex = min(kTile, B.nx - ox), ey = min(kTile, B.ny - oy), ez = min(kTile, B.nz - oz);
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
@@ -510,8 +549,10 @@ __global__ __launch_bounds__(kSpreadBlock) void k_spread(Dev d) {
 template <int NW>
 __global__ __launch_bounds__(kInterpBlock) void k_interp_advance(Dev d) {
   constexpr int L = NW == 2 ? 8 : (NW == 3 ? 32 : 64);
-  if (blockIdx.x == 0 && threadIdx.x == 0)
-    atomicAdd(reinterpret_cast<unsigned long long*>(d.step), 1ull);
+  // the next bead statistics (step *d.step + d.sub) list near blocks under
+  // that step's parity; the list was last read by the active launch that
+  // preceded this kernel
+  if (blockIdx.x == 0 && threadIdx.x == 0) d.near_count[(int)((*d.step + d.sub) & 1)] = 0;
   const int gid = blockIdx.x * kInterpBlock + threadIdx.x;
   const int m = gid / L, lane = gid % L;
   float ux = 0, uy = 0, uz = 0;
@@ -562,10 +603,10 @@ __global__ __launch_bounds__(kStatsBlock) void k_bead_centres(Dev d, double* out
 
 }  // namespace
 
-void launch_bead_stats(const Dev& d, hipStream_t s) {
-  if (d.width == 2) hipLaunchKernelGGL(k_bead_stats<2>, dim3(d.nbeads), dim3(kStatsBlock), 0, s, d);
-  else if (d.width == 3) hipLaunchKernelGGL(k_bead_stats<3>, dim3(d.nbeads), dim3(kStatsBlock), 0, s, d);
-  else hipLaunchKernelGGL(k_bead_stats<4>, dim3(d.nbeads), dim3(kStatsBlock), 0, s, d);
+void launch_bead_stats(const Dev& d, int mark_offset, hipStream_t s) {
+  if (d.width == 2) hipLaunchKernelGGL(k_bead_stats<2>, dim3(d.nbeads), dim3(kStatsBlock), 0, s, d, mark_offset);
+  else if (d.width == 3) hipLaunchKernelGGL(k_bead_stats<3>, dim3(d.nbeads), dim3(kStatsBlock), 0, s, d, mark_offset);
+  else hipLaunchKernelGGL(k_bead_stats<4>, dim3(d.nbeads), dim3(kStatsBlock), 0, s, d, mark_offset);
 }
 
 void launch_vertex_forces(const Dev& d, hipStream_t s) {

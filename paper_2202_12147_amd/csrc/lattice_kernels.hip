@@ -124,96 +124,127 @@ __device__ inline int logical_block(int remap, int nblocks) {
   return (blockIdx.x % 8) * per + blockIdx.x / 8;
 }
 
-template <int ST, int BS>
-__global__ __launch_bounds__(BS) void k_stream_collide(Dev d, int tick, int remap, int nblocks) {
+// One node of the fused step: pull, moments, forcing, BGK collision, store.
+// `forced`: read F and write u at this node (its tile is active this step).
+template <int ST>
+__device__ inline void sc_node(const Dev& d, const Box& B, int x, int y, int z, int64_t base,
+                               int64_t n, bool forced) {
   using IO = PopIO<ST>;
   using T = typename IO::T;
-  const int blk = logical_block(remap, nblocks);
-  const int64_t n = *d.step;
-  const int b = (d.nboxes == 1 || blk >= nblocks) ? 0 : d.sc_block_box[blk];
+  const Nbr o = neighbours(x, y, z, B.nx, B.ny, B.nz);
+  const T* __restrict__ src = static_cast<const T*>(d.pop[n & 1]);
+  T* __restrict__ dst = static_cast<T*>(d.pop[(n + 1) & 1]);
+  const int64_t ps = d.pstride;
+  float g[kQ];
+  pull<ST>(src, ps, base, o, d.fp16_inv, g);
+  const Moments m = moments(g);
+
+  float Fx = B.gx, Fy = B.gy, Fz = B.gz;
+  if (forced) {
+    Fx += d.F[base];
+    Fy += d.F[ps + base];
+    Fz += d.F[2 * ps + base];
+  }
+  const float ir = 1.0f / m.rho;
+  const float ux = (m.jx + 0.5f * Fx) * ir;
+  const float uy = (m.jy + 0.5f * Fy) * ir;
+  const float uz = (m.jz + 0.5f * Fz) * ir;
+  if (forced) {
+    d.u[base] = ux;
+    d.u[ps + base] = uy;
+    d.u[2 * ps + base] = uz;
+  }
+  float ex = ux, ey = uy, ez = uz, src_a = 1.0f - 0.5f * B.omega;
+  if (B.forcing == kShanChen) {
+    ex = (m.jx + B.tau * Fx) * ir;
+    ey = (m.jy + B.tau * Fy) * ir;
+    ez = (m.jz + B.tau * Fz) * ir;
+    src_a = 0.0f;
+  }
+  const float om = B.omega;
+  const float usq15 = 1.5f * (ex * ex + ey * ey + ez * ez);
+  const float uf = ux * Fx + uy * Fy + uz * Fz;
+  // rest population
+  {
+    const float eq0 = kW0 * (m.drho - m.rho * usq15);
+    g[0] = g[0] + om * (eq0 - g[0]) + src_a * kW0 * (-3.0f * uf);
+  }
+  // faces
+  collide_pair(g[1], g[2], kW1, om, m.drho, m.rho, usq15, ex, src_a, ux, Fx, uf);
+  collide_pair(g[3], g[4], kW1, om, m.drho, m.rho, usq15, ey, src_a, uy, Fy, uf);
+  collide_pair(g[5], g[6], kW1, om, m.drho, m.rho, usq15, ez, src_a, uz, Fz, uf);
+  // edges
+  collide_pair(g[7], g[8], kW2, om, m.drho, m.rho, usq15, ex + ey, src_a, ux + uy, Fx + Fy, uf);
+  collide_pair(g[9], g[10], kW2, om, m.drho, m.rho, usq15, ex - ey, src_a, ux - uy, Fx - Fy, uf);
+  collide_pair(g[11], g[12], kW2, om, m.drho, m.rho, usq15, ex + ez, src_a, ux + uz, Fx + Fz, uf);
+  collide_pair(g[13], g[14], kW2, om, m.drho, m.rho, usq15, ex - ez, src_a, ux - uz, Fx - Fz, uf);
+  collide_pair(g[15], g[16], kW2, om, m.drho, m.rho, usq15, ey + ez, src_a, uy + uz, Fy + Fz, uf);
+  collide_pair(g[17], g[18], kW2, om, m.drho, m.rho, usq15, ey - ez, src_a, uy - uz, Fy - Fz, uf);
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) IO::st(dst + q * ps + base, g[q], d.fp16_scale);
+}
+
+// Launch modes of the fused step:
+//   kScAll    every node of the grid; F and u where the node's tile is
+//             stamped active for this step (used without concurrent IBM work);
+//   kScBulk   every block except those marked near at the previous step,
+//             never forced; persistent when `resident` > 0 (each XCD walks one
+//             contiguous range of blocks, leaving workgroup slots free for the
+//             concurrent immersed-boundary kernels);
+//   kScActive one workgroup per listed near block, forced where the node's
+//             tile is active.
+constexpr int kScAll = kLaunchAll, kScBulk = kLaunchBulk, kScActive = kLaunchActive;
+
+template <int ST, int BS>
+__device__ inline void sc_block(const Dev& d, int blk, int64_t n, bool bulk) {
+  const int b = d.nboxes == 1 ? 0 : d.sc_block_box[blk];
   const Box B = d.boxes[b];
   const int first = d.nboxes == 1 ? 0 : d.sc_box_block0[b];
   const int id = (blk - first) * BS + (int)threadIdx.x;
-  if (blk < nblocks && id < B.n) {
-    const int nx = B.nx, ny = B.ny, nz = B.nz;
-    const int x = id % nx;
-    const int yz = id / nx;
-    const int y = yz % ny;
-    const int z = yz / ny;
-    const Nbr o = neighbours(x, y, z, nx, ny, nz);
-    const T* __restrict__ src = static_cast<const T*>(d.pop[n & 1]);
-    T* __restrict__ dst = static_cast<T*>(d.pop[(n + 1) & 1]);
-    const int64_t ps = d.pstride;
-    const int64_t base = B.node0 + id;
-    float g[kQ];
-    pull<ST>(src, ps, base, o, d.fp16_inv, g);
-    const Moments m = moments(g);
-
-    float Fx = B.gx, Fy = B.gy, Fz = B.gz;
+  if (id >= B.n) return;
+  const int x = id % B.nx;
+  const int yz = id / B.nx;
+  const int y = yz % B.ny;
+  const int z = yz / B.ny;
+  // nodes of the bulk launch are never forced: every node a stencil reaches
+  // lies in a near block, and an active tile's other nodes carry F = 0
+  bool forced = false;
+  if (!bulk) {
     const int tile = B.tile0 + (x / kTile) + B.tx * ((y / kTile) + B.ty * (z / kTile));
-    const bool active = d.stamp[tile] == (int)n;
-    if (active) {
-      Fx += d.F[base];
-      Fy += d.F[ps + base];
-      Fz += d.F[2 * ps + base];
-    }
-    const float ir = 1.0f / m.rho;
-    const float ux = (m.jx + 0.5f * Fx) * ir;
-    const float uy = (m.jy + 0.5f * Fy) * ir;
-    const float uz = (m.jz + 0.5f * Fz) * ir;
-    if (active) {
-      d.u[base] = ux;
-      d.u[ps + base] = uy;
-      d.u[2 * ps + base] = uz;
-    }
-    float ex = ux, ey = uy, ez = uz, src_a = 1.0f - 0.5f * B.omega;
-    if (B.forcing == kShanChen) {
-      ex = (m.jx + B.tau * Fx) * ir;
-      ey = (m.jy + B.tau * Fy) * ir;
-      ez = (m.jz + B.tau * Fz) * ir;
-      src_a = 0.0f;
-    }
-    const float om = B.omega;
-    const float usq15 = 1.5f * (ex * ex + ey * ey + ez * ez);
-    const float uf = ux * Fx + uy * Fy + uz * Fz;
-    // rest population
-    {
-      const float eq0 = kW0 * (m.drho - m.rho * usq15);
-      g[0] = g[0] + om * (eq0 - g[0]) + src_a * kW0 * (-3.0f * uf);
-    }
-    // faces
-    collide_pair(g[1], g[2], kW1, om, m.drho, m.rho, usq15, ex, src_a, ux, Fx, uf);
-    collide_pair(g[3], g[4], kW1, om, m.drho, m.rho, usq15, ey, src_a, uy, Fy, uf);
-    collide_pair(g[5], g[6], kW1, om, m.drho, m.rho, usq15, ez, src_a, uz, Fz, uf);
-    // edges
-    collide_pair(g[7], g[8], kW2, om, m.drho, m.rho, usq15, ex + ey, src_a, ux + uy, Fx + Fy, uf);
-    collide_pair(g[9], g[10], kW2, om, m.drho, m.rho, usq15, ex - ey, src_a, ux - uy, Fx - Fy, uf);
-    collide_pair(g[11], g[12], kW2, om, m.drho, m.rho, usq15, ex + ez, src_a, ux + uz, Fx + Fz, uf);
-    collide_pair(g[13], g[14], kW2, om, m.drho, m.rho, usq15, ex - ez, src_a, ux - uz, Fx - Fz, uf);
-    collide_pair(g[15], g[16], kW2, om, m.drho, m.rho, usq15, ey + ez, src_a, uy + uz, Fy + Fz, uf);
-    collide_pair(g[17], g[18], kW2, om, m.drho, m.rho, usq15, ey - ez, src_a, uy - uz, Fy - Fz, uf);
-#pragma unroll
-    for (int q = 0; q < kQ; ++q) IO::st(dst + q * ps + base, g[q], d.fp16_scale);
+    forced = d.stamp[tile] == (int)n;
   }
-  if (tick) {
-    // the last block to finish advances the step counter; every block has
-    // read it by then
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      __threadfence();
-      const unsigned prev = atomicAdd(d.done, 1u);
-      if (prev == gridDim.x - 1) {
-        atomicExch(d.done, 0u);
-        atomicExch(reinterpret_cast<unsigned long long*>(d.step),
-                   static_cast<unsigned long long>(n + 1));
+  sc_node<ST>(d, B, x, y, z, B.node0 + id, n, forced);
+}
+
+template <int ST, int BS, int MODE>
+__global__ __launch_bounds__(BS) void k_stream_collide(Dev d, int remap, int nblocks, int resident) {
+  const int64_t n = *d.step + d.sub;
+  const int64_t pn = n - 1;  // the step whose bead statistics marked the near blocks
+  const int pp = (int)(pn & 1);
+  if constexpr (MODE == kScActive) {
+    const int cnt = min(d.near_count[pp], d.max_near);
+    if ((int)blockIdx.x < cnt) sc_block<ST, BS>(d, d.near_list[pp * d.max_near + blockIdx.x], n, false);
+  } else if constexpr (MODE == kScBulk) {
+    if (resident) {
+      const int per = (nblocks + 7) / 8;  // logical blocks per XCD
+      const int xcd = blockIdx.x % 8, g8 = (int)gridDim.x / 8;
+      for (int j = blockIdx.x / 8; j < per; j += g8) {
+        const int blk = xcd * per + j;
+        if (blk < nblocks && d.near[pp * d.nsc + blk] != (int)pn) sc_block<ST, BS>(d, blk, n, true);
       }
+    } else {
+      const int blk = logical_block(remap, nblocks);
+      if (blk < nblocks && d.near[pp * d.nsc + blk] != (int)pn) sc_block<ST, BS>(d, blk, n, true);
     }
+  } else {
+    const int blk = logical_block(remap, nblocks);
+    if (blk < nblocks) sc_block<ST, BS>(d, blk, n, false);
   }
 }
 
-__global__ void k_tick(int64_t* step) {
-  if (threadIdx.x == 0 && blockIdx.x == 0)
-    atomicAdd(reinterpret_cast<unsigned long long*>(step), 1ull);
+// Advance the step counter past an enqueued chunk of `count` steps.
+__global__ void k_tick(int64_t* step, int count) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *step += count;
 }
 
 // u_n and rho_n of the last completed step n = step - 1 (zero before any step).
@@ -345,27 +376,42 @@ void launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t s) {
                      static_cast<f32x4*>(dst), n);
 }
 
-template <int ST>
-static void launch_sc_st(const Dev& d, int block, int nblocks, int tick, int remap, hipStream_t s) {
-  const int grid = remap ? (nblocks + 7) / 8 * 8 : nblocks;
-  if (block == 128)
-    hipLaunchKernelGGL((k_stream_collide<ST, 128>), dim3(grid), dim3(128), 0, s, d, tick, remap, nblocks);
-  else if (block == 512)
-    hipLaunchKernelGGL((k_stream_collide<ST, 512>), dim3(grid), dim3(512), 0, s, d, tick, remap, nblocks);
-  else
-    hipLaunchKernelGGL((k_stream_collide<ST, 256>), dim3(grid), dim3(256), 0, s, d, tick, remap, nblocks);
-}
-
-void launch_stream_collide(const Dev& d, int storage, int block, int nblocks, int tick, int remap,
+template <int ST, int MODE>
+static void launch_sc_mode(const Dev& d, int block, int nblocks, int remap, int resident, int ncu,
                            hipStream_t s) {
-  if (storage == kFp16)
-    launch_sc_st<kFp16>(d, block, nblocks, tick, remap, s);
+  int grid = remap ? (nblocks + 7) / 8 * 8 : nblocks;
+  if (MODE == kScActive) grid = d.max_near;
+  if (MODE == kScBulk && resident > 0) grid = std::min(grid, ncu * resident) / 8 * 8;
+  if (MODE != kScBulk) resident = 0;
+  if (block == 128)
+    hipLaunchKernelGGL((k_stream_collide<ST, 128, MODE>), dim3(grid), dim3(128), 0, s, d, remap, nblocks, resident);
+  else if (block == 512)
+    hipLaunchKernelGGL((k_stream_collide<ST, 512, MODE>), dim3(grid), dim3(512), 0, s, d, remap, nblocks, resident);
   else
-    launch_sc_st<kFp32>(d, block, nblocks, tick, remap, s);
+    hipLaunchKernelGGL((k_stream_collide<ST, 256, MODE>), dim3(grid), dim3(256), 0, s, d, remap, nblocks, resident);
 }
 
-void launch_tick(const Dev& d, hipStream_t s) {
-  hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, s, d.step);
+template <int ST>
+static void launch_sc_st(const Dev& d, int mode, int block, int nblocks, int remap, int resident,
+                         int ncu, hipStream_t s) {
+  if (mode == kScBulk)
+    launch_sc_mode<ST, kScBulk>(d, block, nblocks, remap, resident, ncu, s);
+  else if (mode == kScActive)
+    launch_sc_mode<ST, kScActive>(d, block, nblocks, remap, resident, ncu, s);
+  else
+    launch_sc_mode<ST, kScAll>(d, block, nblocks, remap, resident, ncu, s);
+}
+
+void launch_stream_collide(const Dev& d, int storage, int mode, int block, int nblocks, int remap,
+                           int resident, int ncu, hipStream_t s) {
+  if (storage == kFp16)
+    launch_sc_st<kFp16>(d, mode, block, nblocks, remap, resident, ncu, s);
+  else
+    launch_sc_st<kFp32>(d, mode, block, nblocks, remap, resident, ncu, s);
+}
+
+void launch_tick(const Dev& d, int count, hipStream_t s) {
+  hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, s, d.step, count);
 }
 
 void launch_velocity(const Dev& d, int storage, int nblocks, float* u_out, float* rho_out,

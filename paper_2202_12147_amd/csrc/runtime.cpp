@@ -137,7 +137,8 @@ struct lbm_handle {
   int nm = 0;
   int64_t nodes = 0, pstride = 0;
   int ntiles = 0, sc_blocks = 0, spread_blocks = 0, out_blocks = 0;
-  int sc_block = 256, sc_remap = 1;  // stream-collide launch shape
+  int sc_block = 256, sc_remap = 1, sc_resident = 0;  // stream-collide launch shape
+  int ncu = 256;                                        // compute units of the device
   bool uploaded = false, stepped = false;
   int64_t host_step = 0;  // steps enqueued
 
@@ -148,7 +149,6 @@ struct lbm_handle {
   Box* d_boxes = nullptr;
   int* d_block_box = nullptr;
   int64_t* d_step = nullptr;
-  unsigned* d_done = nullptr;
   double* d_pos = nullptr;
   float *d_U = nullptr, *d_fm = nullptr;
   Bead* d_beads = nullptr;
@@ -160,6 +160,10 @@ struct lbm_handle {
   int *d_vt_off = nullptr, *d_vt = nullptr, *d_vh_off = nullptr, *d_vh = nullptr;
   int* d_overflow = nullptr;
   int* d_spread_bead = nullptr;
+  int *d_near = nullptr, *d_near_list = nullptr, *d_near_count = nullptr;
+  bool need_prologue = true;
+  hipStream_t side = nullptr;      // IBM chain, forked from `stream` every step
+  std::vector<hipEvent_t> fork_join;
   double *d_partial = nullptr, *d_out = nullptr, *d_centres = nullptr;
   std::vector<void*> allocs;
 
@@ -198,6 +202,23 @@ int element_bytes(const lbm_handle* h) { return h->storage == LBM_FP16_SHIFTED ?
 int reserved_tiles(double radius, int width, int T) {
   const int span = (int)std::floor(2.0 * radius * 1.25) + width + 2;
   return std::min(T, (span + kTile - 2) / kTile + 1);
+}
+
+// Stream-collide block geometry and the bound on near blocks: per bead the
+// marked node box is its reserved tile span plus two nodes each side.
+void set_near_bounds(lbm_handle* h) {
+  Dev& d = h->dev;
+  d.nsc = h->sc_blocks;
+  d.sc_bs = h->sc_block;
+  int64_t mx = 0;
+  const Box& B = h->boxes[0];
+  for (const Bead& b : h->beads) {
+    const int64_t sx = std::min<int64_t>(b.tiles_x * kTile + 4, B.nx);
+    const int64_t sy = std::min<int64_t>(b.tiles_y * kTile + 4, B.ny);
+    const int64_t sz = std::min<int64_t>(b.tiles_z * kTile + 4, B.nz);
+    mx += sy * sz * (sx / h->sc_block + 2);
+  }
+  d.max_near = (int)std::max<int64_t>(1, std::min<int64_t>(mx, d.nsc));
 }
 
 int upload(lbm_handle* h) {
@@ -280,6 +301,11 @@ int upload(lbm_handle* h) {
   h->d_vh = h->alloc<int>(vhf.size(), rc);
   h->d_spread_bead = h->alloc<int>(spread_bead.size(), rc);
   h->d_centres = h->alloc<double>(3 * h->beads.size(), rc);
+  // near-block buffers, sized for the smallest stream-collide block (128)
+  const int64_t nsc_max = (h->nodes + 127) / 128;
+  h->d_near = h->alloc<int>(2 * (size_t)nsc_max, rc);
+  h->d_near_list = h->alloc<int>(2 * (size_t)nsc_max, rc);
+  h->d_near_count = h->alloc<int>(2, rc);
   if (rc != LBM_OK) return h->fail(rc, "device allocation for markers failed");
   put(h->d_boxes, h->boxes.data(), sizeof(Box) * h->boxes.size());
   put(h->d_pos, pos.data(), sizeof(double) * pos.size());
@@ -337,41 +363,114 @@ int upload(lbm_handle* h) {
   d.vh = h->d_vh;
   d.spread_blocks = h->spread_blocks;
   d.spread_bead = h->d_spread_bead;
+  d.near = h->d_near;
+  d.near_list = h->d_near_list;
+  d.near_count = h->d_near_count;
+  d.tile_box = nullptr;
+  set_near_bounds(h);
+  if (!h->swimmers.empty()) {
+    rc = h->hip(hipStreamCreate(&h->side), "hipStreamCreate");
+    if (rc) return rc;
+    h->fork_join.resize(2 * kGraphChunk);
+    for (auto& e : h->fork_join) {
+      rc = h->hip(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreateWithFlags");
+      if (rc) return rc;
+    }
+  }
   h->uploaded = true;
+  h->need_prologue = true;
   return LBM_OK;
 }
 
-// Enqueue one step.  With swimmers: bead statistics -> nodal forces ->
-// spreading -> stream-collide -> interpolation + advection (which also
-// advances the device step counter).  Without: stream-collide advances it.
-void enqueue_step(lbm_handle* h) {
-  const Dev& d = h->dev;
-  const bool ibm = !h->swimmers.empty();
-  if (ibm) {
-    launch_bead_stats(d, h->stream);
-    launch_vertex_forces(d, h->stream);
-    launch_spread(d, h->stream);
-  }
-  if (h->timing) {
-    if (h->ev_used + 2 > h->ev_pool.size()) {
-      for (int i = 0; i < 64; ++i) {
-        hipEvent_t e;
-        (void)hipEventCreate(&e);
-        h->ev_pool.push_back(e);
-      }
+void timing_event(lbm_handle* h) {
+  if (h->ev_used + 1 > h->ev_pool.size()) {
+    for (int i = 0; i < 64; ++i) {
+      hipEvent_t e;
+      (void)hipEventCreate(&e);
+      h->ev_pool.push_back(e);
     }
-    (void)hipEventRecord(h->ev_pool[h->ev_used++], h->stream);
   }
-  launch_stream_collide(d, h->storage, h->sc_block, h->sc_blocks, ibm ? 0 : 1, h->sc_remap, h->stream);
-  if (h->timing) (void)hipEventRecord(h->ev_pool[h->ev_used++], h->stream);
-  if (ibm) launch_interp_advance(d, h->stream);
+  (void)hipEventRecord(h->ev_pool[h->ev_used++], h->stream);
+}
+
+// Enqueue `count` steps.  Without swimmers each step is one full-grid
+// stream-collide launch.  With swimmers, step k forks the IBM chain onto the
+// side stream -- advection of the previous step, bead statistics, nodal
+// forces, spreading -- while the main stream streams and collides every node
+// away from the swimmers; the active-tile launch then joins both and advances
+// the step counter.  The last step's advection closes the sequence, so the
+// markers are current whenever the sequence ends.
+void enqueue_steps(lbm_handle* h, int64_t count) {
+  Dev d = h->dev;
+  if (h->swimmers.empty()) {
+    for (int64_t i = 0; i < count; ++i) {
+      d.sub = (int)i;
+      if (h->timing) timing_event(h);
+      launch_stream_collide(d, h->storage, kLaunchAll, h->sc_block, h->sc_blocks, h->sc_remap, 0, h->ncu, h->stream);
+      if (h->timing) timing_event(h);
+    }
+    launch_tick(d, (int)count, h->stream);
+    return;
+  }
+  if (h->sc_resident < 0) {
+    // serial order: the immersed-boundary chain, then the full grid
+    for (int64_t i = 0; i < count; ++i) {
+      d.sub = (int)i;
+      launch_bead_stats(d, 0, h->stream);
+      launch_vertex_forces(d, h->stream);
+      launch_spread(d, h->stream);
+      if (h->timing) timing_event(h);
+      launch_stream_collide(d, h->storage, kLaunchAll, h->sc_block, h->sc_blocks, h->sc_remap, 0, h->ncu, h->stream);
+      if (h->timing) timing_event(h);
+      d.sub = (int)i + 1;
+      launch_interp_advance(d, h->stream);
+    }
+    launch_tick(d, (int)count, h->stream);
+    return;
+  }
+  for (int64_t i = 0; i < count; ++i) {
+    hipEvent_t fork = h->fork_join[2 * (i % kGraphChunk)], join = h->fork_join[2 * (i % kGraphChunk) + 1];
+    (void)hipEventRecord(fork, h->stream);
+    (void)hipStreamWaitEvent(h->side, fork, 0);
+    d.sub = (int)i;
+    if (i > 0) launch_interp_advance(d, h->side);
+    launch_bead_stats(d, 0, h->side);
+    launch_vertex_forces(d, h->side);
+    launch_spread(d, h->side);
+    (void)hipEventRecord(join, h->side);
+    if (h->timing) timing_event(h);
+    launch_stream_collide(d, h->storage, kLaunchBulk, h->sc_block, h->sc_blocks, h->sc_remap, h->sc_resident,
+                          h->ncu, h->stream);
+    if (h->timing) timing_event(h);
+    (void)hipStreamWaitEvent(h->stream, join, 0);
+    if (h->timing) timing_event(h);
+    launch_stream_collide(d, h->storage, kLaunchActive, h->sc_block, h->sc_blocks, 0, 0, h->ncu, h->stream);
+    if (h->timing) timing_event(h);
+  }
+  d.sub = (int)count;
+  launch_interp_advance(d, h->stream);
+  launch_tick(d, (int)count, h->stream);
+}
+
+// Before stepping resumes: bead regions of the current markers and the near
+// tiles under the previous step's parity, so the first step can split the
+// grid into bulk and active parts.  Eager, never captured.
+int prologue(lbm_handle* h) {
+  if (!h->need_prologue || h->swimmers.empty()) return LBM_OK;
+  int rc = h->hip(hipMemsetAsync(h->d_near, 0x80, sizeof(int) * 2 * h->dev.nsc, h->stream), "hipMemsetAsync");
+  if (!rc) rc = h->hip(hipMemsetAsync(h->d_near_count, 0, sizeof(int) * 2, h->stream), "hipMemsetAsync");
+  if (rc) return rc;
+  launch_bead_stats(h->dev, -1, h->stream);
+  rc = h->hip(hipGetLastError(), "prologue launch");
+  if (!rc) h->need_prologue = false;
+  return rc;
 }
 
 int capture(lbm_handle* h, int steps, hipGraphExec_t* out) {
   hipGraph_t g = nullptr;
   int rc = h->hip(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
   if (rc) return rc;
-  for (int i = 0; i < steps; ++i) enqueue_step(h);
+  enqueue_steps(h, steps);
   rc = h->hip(hipStreamEndCapture(h->stream, &g), "hipStreamEndCapture");
   if (rc) return rc;
   rc = h->hip(hipGraphInstantiate(out, g, nullptr, nullptr, 0), "hipGraphInstantiate");
@@ -399,7 +498,8 @@ int check_overflow(lbm_handle* h) {
   if (rc) return rc;
   rc = h->hip(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
   if (rc) return rc;
-  if (ov) return h->fail(LBM_EOVERFLOW, "a bead outgrew its reserved tile region");
+  if (ov & 1) return h->fail(LBM_EOVERFLOW, "a bead outgrew its reserved tile region");
+  if (ov & 2) return h->fail(LBM_EOVERFLOW, "near-block list overflow");
   return LBM_OK;
 }
 
@@ -443,6 +543,8 @@ int lbm_create(const lbm_grid* grid, double tau, int forcing, const lbm_opts* op
   h->fp16_scale = o.fp16_scale;
   h->use_graphs = o.use_graphs != 0;
   int rc = h->hip(hipGetDevice(&h->device), "hipGetDevice");
+  if (!rc) rc = h->hip(hipDeviceGetAttribute(&h->ncu, hipDeviceAttributeMultiprocessorCount, h->device),
+                      "hipDeviceGetAttribute");
   if (rc) {
     delete h;
     return rc;
@@ -486,7 +588,6 @@ int lbm_create(const lbm_grid* grid, double tau, int forcing, const lbm_opts* op
   h->stamp = h->alloc<int>(h->ntiles, rc);
   h->d_boxes = h->alloc<Box>(1, rc);
   h->d_step = h->alloc<int64_t>(1, rc);
-  h->d_done = h->alloc<unsigned>(1, rc);
   h->d_overflow = h->alloc<int>(1, rc);
   h->d_partial = h->alloc<double>(4 * kReduceParts, rc);
   h->d_out = h->alloc<double>(4, rc);
@@ -498,9 +599,8 @@ int lbm_create(const lbm_grid* grid, double tau, int forcing, const lbm_opts* op
   if (!rc) rc = h->hip(hipMemset(h->pop[1], 0, eb * kQ * h->pstride), "hipMemset");
   if (!rc) rc = h->hip(hipMemset(h->F, 0, sizeof(float) * 3 * h->pstride), "hipMemset");
   if (!rc) rc = h->hip(hipMemset(h->u, 0, sizeof(float) * 3 * h->pstride), "hipMemset");
-  if (!rc) rc = h->hip(hipMemset(h->stamp, 0xff, sizeof(int) * h->ntiles), "hipMemset");
+  if (!rc) rc = h->hip(hipMemset(h->stamp, 0x80, sizeof(int) * h->ntiles), "hipMemset");
   if (!rc) rc = h->hip(hipMemset(h->d_step, 0, sizeof(int64_t)), "hipMemset");
-  if (!rc) rc = h->hip(hipMemset(h->d_done, 0, sizeof(unsigned)), "hipMemset");
   if (!rc) rc = h->hip(hipMemset(h->d_overflow, 0, sizeof(int)), "hipMemset");
   if (!rc) rc = h->hip(hipMemcpy(h->d_boxes, h->boxes.data(), sizeof(Box), hipMemcpyHostToDevice), "hipMemcpy");
   if (!rc) rc = h->hip(hipDeviceSynchronize(), "hipDeviceSynchronize");
@@ -519,7 +619,7 @@ int lbm_create(const lbm_grid* grid, double tau, int forcing, const lbm_opts* op
   d.nboxes = 1;
   d.block_box = nullptr;
   d.step = h->d_step;
-  d.done = h->d_done;
+  d.sub = 0;
   d.fp16_scale = h->fp16_scale;
   d.fp16_inv = 1.0f / h->fp16_scale;
   d.width = h->width;
@@ -534,6 +634,8 @@ int lbm_destroy(lbm_handle* h) {
   if (h->g_chunk) (void)hipGraphExecDestroy(h->g_chunk);
   if (h->g_one) (void)hipGraphExecDestroy(h->g_one);
   for (auto e : h->ev_pool) (void)hipEventDestroy(e);
+  for (auto e : h->fork_join) (void)hipEventDestroy(e);
+  if (h->side) (void)hipStreamDestroy(h->side);
   for (void* p : h->allocs) (void)hipFree(p);
   if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
   delete h;
@@ -659,9 +761,11 @@ int lbm_step(lbm_handle* h, int64_t n) {
   if (!h || n < 0) return LBM_EINVAL;
   int rc = upload(h);
   if (rc) return rc;
+  rc = prologue(h);
+  if (rc) return rc;
   h->stepped = true;
   if (h->timing || !h->use_graphs) {
-    for (int64_t i = 0; i < n; ++i) enqueue_step(h);
+    for (int64_t done = 0; done < n; done += kGraphChunk) enqueue_steps(h, std::min<int64_t>(kGraphChunk, n - done));
     h->host_step += n;
     if (h->timing && h->ev_used > 256) harvest_timing(h);
     return h->hip(hipGetLastError(), "kernel launch");
@@ -907,7 +1011,10 @@ int checkpoint(lbm_handle* h, const char* path, bool save) {
     if (!rc) rc = io_blob(h, f, h->d_bstate, sizeof(BeadState) * h->beads.size(), save);
   }
   fclose(f);
-  if (!rc && !save) h->stepped = true;
+  if (!rc && !save) {
+    h->stepped = true;
+    h->need_prologue = true;
+  }
   return rc;
 }
 }  // namespace
@@ -965,14 +1072,17 @@ int lbm_probe_copy_bandwidth(int64_t bytes, int iters, double* gbs) {
   return rc;
 }
 
-int lbm_set_stream_collide_launch(lbm_handle* h, int block, int xcd_remap) {
-  if (!h || (block != 128 && block != 256 && block != 512)) return LBM_EINVAL;
+int lbm_set_stream_collide_launch(lbm_handle* h, int block, int xcd_remap, int resident) {
+  if (!h || (block != 128 && block != 256 && block != 512) || resident < -1 || resident > 64) return LBM_EINVAL;
   if (h->boxes.size() != 1) return h->fail(LBM_ESTATE, "launch shape of a batch is set by its tuner");
   int rc = h->hip(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
   if (rc) return rc;
   h->sc_block = block;
   h->sc_remap = xcd_remap ? 1 : 0;
+  h->sc_resident = resident;
   h->sc_blocks = (int)((h->nodes + block - 1) / block);
+  set_near_bounds(h);
+  h->need_prologue = true;
   if (h->g_chunk) (void)hipGraphExecDestroy(h->g_chunk);
   if (h->g_one) (void)hipGraphExecDestroy(h->g_one);
   h->g_chunk = h->g_one = nullptr;

@@ -110,7 +110,7 @@ def load_library():
         "lbm_kernel_time": (C.c_int, [vp, C.POINTER(C.c_double), C.POINTER(i64)]),
         "lbm_bytes_per_step": (i64, [vp]),
         "lbm_probe_copy_bandwidth": (C.c_int, [i64, C.c_int, C.POINTER(C.c_double)]),
-        "lbm_set_stream_collide_launch": (C.c_int, [vp, C.c_int, C.c_int]),
+        "lbm_set_stream_collide_launch": (C.c_int, [vp, C.c_int, C.c_int, C.c_int]),
         "lbm_strerror": (C.c_char_p, [C.c_int]),
         "lbm_last_error": (C.c_char_p, [vp]),
     }
@@ -302,8 +302,9 @@ class Lattice:
         self._check(self.lib.lbm_kernel_time(self.h, C.byref(ms), C.byref(n)))
         return ms.value, n.value
 
-    def set_stream_collide_launch(self, block=256, xcd_remap=False):
-        self._check(self.lib.lbm_set_stream_collide_launch(self.h, int(block), int(bool(xcd_remap))))
+    def set_stream_collide_launch(self, block=256, xcd_remap=True, resident=0):
+        self._check(self.lib.lbm_set_stream_collide_launch(self.h, int(block), int(bool(xcd_remap)),
+                                                           int(resident)))
 
     @property
     def bytes_per_step(self):

@@ -131,7 +131,7 @@ def test_launch_shapes_bitwise_equal(block, remap):
     dev = wl.random_deviation(shape, 6, 1e-4)
     a = lbmib.Lattice(shape, 0.9, use_graphs=False)
     b = lbmib.Lattice(shape, 0.9)
-    b.set_stream_collide_launch(block, remap)
+    b.set_stream_collide_launch(block, remap, 0)
     for x in (a, b):
         x.set_populations(dev)
         x.set_body_force((1e-6, 2e-6, 0))

@@ -112,3 +112,22 @@ def test_swimmer_add_after_step_rejected():
     with pytest.raises(lbmib.LbmError) as e:
         lat.add_swimmer(case["swimmers"][0])
     assert e.value.code == -4
+
+
+@pytest.mark.parametrize("block,remap,resident", [(128, 0, 0), (256, 1, 2), (512, 1, 1)])
+def test_launch_shapes_bitwise_equal_with_swimmer(block, remap, resident):
+    # the concurrent bulk / active split and its launch shape must not change
+    # a single bit of the result
+    case = wl.single_128(seed=1)
+    case["shape"] = (48, 40, 40)
+    case["swimmers"][0]["centres"] = case["swimmers"][0]["centres"] - (40, 24, 24)
+    a = lbmib.from_workload(case, use_graphs=False)
+    a.set_stream_collide_launch(256, 0, -1)  # serial, unsplit reference order
+    b = lbmib.from_workload(case)
+    b.set_stream_collide_launch(block, remap, resident)
+    for x in (a, b):
+        x.step(45)
+        x.sync()
+    assert np.array_equal(a.markers(), b.markers())
+    assert np.array_equal(a.populations(), b.populations())
+    assert np.array_equal(a.velocity(), b.velocity())
