@@ -104,11 +104,11 @@ struct Dev {
   const int* hinge;      // [4][nh]
   const double* th0cs;   // [2][nh]
   int ntri, nh;
-  // vertex -> incident triangles (tri*3 + corner) and hinges (h*4 + role)
-  const int* vt_off;
-  const int* vt;
-  const int* vh_off;
-  const int* vh;
+  // per node, 32 force lanes: lanes 0..7 incident triangles (element
+  // tri*3 + corner, vertex ids i0 i1 i2), lanes 8..31 hinges (element
+  // h*4 + role, vertex ids x1 x2 x3 x4); element -1 = idle lane
+  const int* lane_elem;  // [nm * 32]
+  const int4* lane_v;    // [nm * 32]
   // stream-collide blocks near the swimmers: flags near[parity][block] = step
   // that marked the block, and per-parity block lists (near_list[parity][i],
   // near_count[parity]); a block is near when it holds a node within two

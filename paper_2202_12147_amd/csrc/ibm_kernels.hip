@@ -129,13 +129,17 @@ __device__ inline void mark_near_blocks(const Dev& d, const Box& B, int box, con
 template <int NW>
 __global__ __launch_bounds__(kStatsBlock) void k_bead_stats(Dev d, int mark_offset) {
   constexpr int NWAVE = kStatsBlock / 64;
-  __shared__ double part[NWAVE][9];
-  __shared__ double cen[3];
+  constexpr int NV = 10;  // sums x y z, min x y z, max x y z, volume
+  __shared__ double part[NWAVE][NV];
   __shared__ int reg_lo[3], reg_hi[3];
   const int b = blockIdx.x;
   const Bead Bd = d.beads[b];
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
-  double v[9] = {0, 0, 0, 1e300, 1e300, 1e300, -1e300, -1e300, -1e300};
+  // The enclosed volume 1/6 sum (r0-c).((r1-c) x (r2-c)) of a closed outward
+  // surface does not depend on the reference point c; the previous step's
+  // centre keeps the products small, and lets one pass reduce everything.
+  const double cx = d.bstate[b].c[0], cy = d.bstate[b].c[1], cz = d.bstate[b].c[2];
+  double v[NV] = {0, 0, 0, 1e300, 1e300, 1e300, -1e300, -1e300, -1e300, 0};
   for (int i = threadIdx.x; i < Bd.nv; i += kStatsBlock) {
     const double3 p = load_pos(d.pos, d.nm, Bd.first + i);
     v[0] += p.x;
@@ -148,30 +152,6 @@ __global__ __launch_bounds__(kStatsBlock) void k_bead_stats(Dev d, int mark_offs
     v[7] = fmax(v[7], p.y);
     v[8] = fmax(v[8], p.z);
   }
-#pragma unroll
-  for (int s = 32; s > 0; s >>= 1) {
-#pragma unroll
-    for (int k = 0; k < 3; ++k) v[k] += __shfl_xor(v[k], s, 64);
-#pragma unroll
-    for (int k = 3; k < 6; ++k) v[k] = fmin(v[k], __shfl_xor(v[k], s, 64));
-#pragma unroll
-    for (int k = 6; k < 9; ++k) v[k] = fmax(v[k], __shfl_xor(v[k], s, 64));
-  }
-  if (lane == 0)
-    for (int k = 0; k < 9; ++k) part[wave][k] = v[k];
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int w = 1; w < NWAVE; ++w) {
-      for (int k = 0; k < 3; ++k) part[0][k] += part[w][k];
-      for (int k = 3; k < 6; ++k) part[0][k] = fmin(part[0][k], part[w][k]);
-      for (int k = 6; k < 9; ++k) part[0][k] = fmax(part[0][k], part[w][k]);
-    }
-    for (int k = 0; k < 3; ++k) cen[k] = part[0][k] / Bd.nv;
-  }
-  __syncthreads();
-  const double cx = cen[0], cy = cen[1], cz = cen[2];
-  // enclosed volume 1/6 sum (r0-c).((r1-c) x (r2-c)) over outward triangles
-  double vol = 0;
   for (int t = threadIdx.x; t < Bd.ntri; t += kStatsBlock) {
     const int tt = Bd.tri0 + t;
     const double3 p0 = load_pos(d.pos, d.nm, d.tri[tt]);
@@ -180,28 +160,37 @@ __global__ __launch_bounds__(kStatsBlock) void k_bead_stats(Dev d, int mark_offs
     const double ax = p0.x - cx, ay = p0.y - cy, az = p0.z - cz;
     const double bx = p1.x - cx, by = p1.y - cy, bz = p1.z - cz;
     const double qx = p2.x - cx, qy = p2.y - cy, qz = p2.z - cz;
-    vol += ax * (by * qz - bz * qy) + ay * (bz * qx - bx * qz) + az * (bx * qy - by * qx);
+    v[9] += ax * (by * qz - bz * qy) + ay * (bz * qx - bx * qz) + az * (bx * qy - by * qx);
   }
-  for (int s = 32; s > 0; s >>= 1) vol += __shfl_xor(vol, s, 64);
-  __syncthreads();
-  if (lane == 0) part[wave][0] = vol;
+#pragma unroll
+  for (int s = 32; s > 0; s >>= 1) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) v[k] += __shfl_xor(v[k], s, 64);
+#pragma unroll
+    for (int k = 3; k < 6; ++k) v[k] = fmin(v[k], __shfl_xor(v[k], s, 64));
+#pragma unroll
+    for (int k = 6; k < 9; ++k) v[k] = fmax(v[k], __shfl_xor(v[k], s, 64));
+    v[9] += __shfl_xor(v[9], s, 64);
+  }
+  if (lane == 0)
+    for (int k = 0; k < NV; ++k) part[wave][k] = v[k];
   __syncthreads();
   if (threadIdx.x == 0) {
-    double V = 0;
-    for (int w = 0; w < NWAVE; ++w) V += part[w][0];
+    for (int w = 1; w < NWAVE; ++w) {
+      for (int k = 0; k < 3; ++k) part[0][k] += part[w][k];
+      for (int k = 3; k < 6; ++k) part[0][k] = fmin(part[0][k], part[w][k]);
+      for (int k = 6; k < 9; ++k) part[0][k] = fmax(part[0][k], part[w][k]);
+      part[0][9] += part[w][9];
+    }
     BeadState& st = d.bstate[b];
     const Box B = d.boxes[Bd.box];
     const int T[3] = {B.tx, B.ty, B.tz};
     const int reserved[3] = {Bd.tiles_x, Bd.tiles_y, Bd.tiles_z};
-    const double lo[3] = {part[0][3], part[0][4], part[0][5]};
-    const double hi[3] = {part[0][6], part[0][7], part[0][8]};
-    st.c[0] = cx;
-    st.c[1] = cy;
-    st.c[2] = cz;
-    st.V = V / 6.0;
+    for (int a = 0; a < 3; ++a) st.c[a] = part[0][a] / Bd.nv;
+    st.V = part[0][9] / 6.0;
     for (int a = 0; a < 3; ++a) {
-      st.lo[a] = stencil_base<NW>(lo[a]);
-      st.hi[a] = stencil_base<NW>(hi[a]) + NW - 1;
+      st.lo[a] = stencil_base<NW>(part[0][3 + a]);
+      st.hi[a] = stencil_base<NW>(part[0][6 + a]) + NW - 1;
       int t0 = floor_div(st.lo[a], kTile);
       int cnt = floor_div(st.hi[a], kTile) - t0 + 1;
       if (cnt >= T[a]) {
@@ -233,9 +222,8 @@ __global__ __launch_bounds__(kStatsBlock) void k_bead_stats(Dev d, int mark_offs
 // dW/de1 = 2 (P11 e1 + P12 e2), dW/de2 = 2 (P12 e1 + P22 e2), e_a = r_a - r_0.
 // Volume: f = -pv * (r_b - c) x (r_c - c) with (corner, b, c) counter-clockwise
 // and pv = kv (V - V0)/(6 V0).
-__device__ inline float3 triangle_corner(const Dev& d, const Bead& Bd, int t, int corner,
-                                         const double* c, float pv) {
-  const int i0 = d.tri[t], i1 = d.tri[d.ntri + t], i2 = d.tri[2 * d.ntri + t];
+__device__ inline float3 triangle_corner(const Dev& d, const Bead& Bd, int t, int corner, int i0, int i1,
+                                         int i2, const double* c, float pv) {
   const double3 p0 = load_pos(d.pos, d.nm, i0);
   const double3 p1 = load_pos(d.pos, d.nm, i1);
   const double3 p2 = load_pos(d.pos, d.nm, i2);
@@ -287,12 +275,12 @@ __device__ inline float3 triangle_corner(const Dev& d, const Bead& Bd, int t, in
 //   d theta/d x2 = -((x1-x3).e^) nA/|nA|^2 + ((x4-x1).e^) nB/|nB|^2.
 // sin(theta - theta0) = sin theta cos theta0 - cos theta sin theta0 with
 // cos theta = nA.nB/(|nA||nB|), sin theta = (nA x nB).e^/(|nA||nB|), in FP64.
-__device__ inline float3 bending_role(const Dev& d, const Bead& Bd, int h, int role) {
+__device__ inline float3 bending_role(const Dev& d, const Bead& Bd, int h, int role, int4 v) {
   const int nh = d.nh;
-  const double3 x1 = load_pos(d.pos, d.nm, d.hinge[h]);
-  const double3 x2 = load_pos(d.pos, d.nm, d.hinge[nh + h]);
-  const double3 x3 = load_pos(d.pos, d.nm, d.hinge[2 * nh + h]);
-  const double3 x4 = load_pos(d.pos, d.nm, d.hinge[3 * nh + h]);
+  const double3 x1 = load_pos(d.pos, d.nm, v.x);
+  const double3 x2 = load_pos(d.pos, d.nm, v.y);
+  const double3 x3 = load_pos(d.pos, d.nm, v.z);
+  const double3 x4 = load_pos(d.pos, d.nm, v.w);
   const double ex = x2.x - x1.x, ey = x2.y - x1.y, ez = x2.z - x1.z;
   const double ax = x3.x - x1.x, ay = x3.y - x1.y, az = x3.z - x1.z;
   const double bx = x4.x - x2.x, by = x4.y - x2.y, bz = x4.z - x2.z;
@@ -365,27 +353,21 @@ __global__ __launch_bounds__(256) void k_vertex_forces(Dev d) {
   int b = 0;
   if (m < d.nm) {
     b = d.marker_bead[m];
-    const Bead Bd = d.beads[b];
-    const BeadState& st = d.bstate[b];
-    if (lane < kVertTriLanes) {
-      const int k = d.vt_off[m] + lane;
-      if (k < d.vt_off[m + 1]) {
-        const int e = d.vt[k];
+    const int e = d.lane_elem[gid];
+    const int4 v = d.lane_v[gid];
+    if (e >= 0) {
+      const Bead Bd = d.beads[b];
+      float3 f;
+      if (lane < kVertTriLanes) {
+        const BeadState& st = d.bstate[b];
         const float pv = (float)(Bd.kv * (st.V - Bd.V0) / (6.0 * Bd.V0));
-        const float3 f = triangle_corner(d, Bd, e / 3, e % 3, st.c, pv);
-        fx = f.x;
-        fy = f.y;
-        fz = f.z;
+        f = triangle_corner(d, Bd, e / 3, e % 3, v.x, v.y, v.z, st.c, pv);
+      } else {
+        f = bending_role(d, Bd, e / 4, e % 4, v);
       }
-    } else {
-      const int k = d.vh_off[m] + lane - kVertTriLanes;
-      if (k < d.vh_off[m + 1]) {
-        const int e = d.vh[k];
-        const float3 f = bending_role(d, Bd, e / 4, e % 4);
-        fx = f.x;
-        fy = f.y;
-        fz = f.z;
-      }
+      fx = f.x;
+      fy = f.y;
+      fz = f.z;
     }
   }
 #pragma unroll
@@ -477,9 +459,14 @@ __global__ __launch_bounds__(kSpreadBlock) void k_spread(Dev d) {
       bool take = false;
       int offx = 0, offy = 0, offz = 0;
       double3 p = make_double3(0, 0, 0);
+      float fmx = 0, fmy = 0, fmz = 0;
       int bx = 0, by = 0, bz = 0;
       if (i < Q.nv) {
-        p = load_pos(d.pos, d.nm, Q.first + i);
+        const int m = Q.first + i;
+        p = load_pos(d.pos, d.nm, m);
+        fmx = d.fm[m];
+        fmy = d.fm[d.nm + m];
+        fmz = d.fm[2 * d.nm + m];
         bx = stencil_base<NW>(p.x);
         by = stencil_base<NW>(p.y);
         bz = stencil_base<NW>(p.z);
@@ -505,10 +492,9 @@ __global__ __launch_bounds__(kSpreadBlock) void k_spread(Dev d) {
           E.w[1][a] = phi<NW>((float)((double)(by + a) - p.y));
           E.w[2][a] = phi<NW>((float)((double)(bz + a) - p.z));
         }
-        const int m = Q.first + i;
-        E.f[0] = d.fm[m];
-        E.f[1] = d.fm[d.nm + m];
-        E.f[2] = d.fm[2 * d.nm + m];
+        E.f[0] = fmx;
+        E.f[1] = fmy;
+        E.f[2] = fmz;
       }
       __syncthreads();
       if (lane < NW * NW * NW) {

@@ -35,7 +35,7 @@ struct PopIO;
 template <>
 struct PopIO<kFp32> {
   using T = float;
-  __device__ static inline float ld(const float* p, float) { return *p; }
+  __device__ static inline float ld(const float* p, float) { return __builtin_nontemporal_load(p); }
   __device__ static inline void st(float* p, float v, float) { __builtin_nontemporal_store(v, p); }
 };
 

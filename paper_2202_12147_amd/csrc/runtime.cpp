@@ -157,7 +157,7 @@ struct lbm_handle {
   int *d_marker_bead = nullptr, *d_tri = nullptr, *d_hinge = nullptr;
   double *d_G0 = nullptr, *d_theta0 = nullptr;
   float *d_G0inv = nullptr, *d_A0 = nullptr, *d_idet = nullptr;
-  int *d_vt_off = nullptr, *d_vt = nullptr, *d_vh_off = nullptr, *d_vh = nullptr;
+  int *d_lane_elem = nullptr, *d_lane_v = nullptr;
   int* d_overflow = nullptr;
   int* d_spread_bead = nullptr;
   int *d_near = nullptr, *d_near_list = nullptr, *d_near_count = nullptr;
@@ -252,15 +252,24 @@ int upload(lbm_handle* h) {
       hinge[k * nh + e] = h->hinge[4 * e + k];
       vh[h->hinge[4 * e + k]].push_back(4 * e + k);
     }
-  std::vector<int> vt_off(nm + 1, 0), vh_off(nm + 1, 0), vtf, vhf;
+  std::vector<int> lane_elem(32 * (size_t)nm, -1);
+  std::vector<int> lane_v(4 * 32 * (size_t)nm, 0);
   for (int m = 0; m < nm; ++m) {
     // the node-force kernel gives each node 8 triangle and 24 hinge lanes
     if (vt[m].size() > 8 || vh[m].size() > 24)
       return h->fail(LBM_EINVAL, "mesh node with more than 8 triangles or 24 hinges");
-    vt_off[m + 1] = vt_off[m] + (int)vt[m].size();
-    vh_off[m + 1] = vh_off[m] + (int)vh[m].size();
-    vtf.insert(vtf.end(), vt[m].begin(), vt[m].end());
-    vhf.insert(vhf.end(), vh[m].begin(), vh[m].end());
+    for (size_t k = 0; k < vt[m].size(); ++k) {
+      const int e = vt[m][k], t = e / 3;
+      const size_t l = 32 * (size_t)m + k;
+      lane_elem[l] = e;
+      for (int q = 0; q < 3; ++q) lane_v[4 * l + q] = h->tri[3 * t + q];
+    }
+    for (size_t k = 0; k < vh[m].size(); ++k) {
+      const int e = vh[m][k], hh = e / 4;
+      const size_t l = 32 * (size_t)m + 8 + k;
+      lane_elem[l] = e;
+      for (int q = 0; q < 4; ++q) lane_v[4 * l + q] = h->hinge[4 * hh + q];
+    }
   }
   std::vector<double> pos(3 * (size_t)nm);
   for (int m = 0; m < nm; ++m)
@@ -295,10 +304,8 @@ int upload(lbm_handle* h) {
   h->d_idet = h->alloc<float>(idet.size(), rc);
   h->d_hinge = h->alloc<int>(hinge.size(), rc);
   h->d_theta0 = h->alloc<double>(2 * h->hingeth0.size(), rc);
-  h->d_vt_off = h->alloc<int>(vt_off.size(), rc);
-  h->d_vt = h->alloc<int>(vtf.size(), rc);
-  h->d_vh_off = h->alloc<int>(vh_off.size(), rc);
-  h->d_vh = h->alloc<int>(vhf.size(), rc);
+  h->d_lane_elem = h->alloc<int>(lane_elem.size(), rc);
+  h->d_lane_v = h->alloc<int>(lane_v.size(), rc);
   h->d_spread_bead = h->alloc<int>(spread_bead.size(), rc);
   h->d_centres = h->alloc<double>(3 * h->beads.size(), rc);
   // near-block buffers, sized for the smallest stream-collide block (128)
@@ -314,6 +321,19 @@ int upload(lbm_handle* h) {
     if (rc == LBM_OK) rc = h->hip(hipMemset(h->d_fm, 0, sizeof(float) * 3 * nm), "hipMemset");
   }
   put(h->d_beads, h->beads.data(), sizeof(Bead) * h->beads.size());
+  {
+    // initial bead state: centre of the stress-free mesh, reference volume
+    std::vector<BeadState> st(h->beads.size());
+    for (size_t b = 0; b < h->beads.size(); ++b) {
+      const Bead& B = h->beads[b];
+      double c[3] = {0, 0, 0};
+      for (int i = 0; i < B.nv; ++i)
+        for (int q = 0; q < 3; ++q) c[q] += h->pos0[3 * (size_t)(B.first + i) + q];
+      for (int q = 0; q < 3; ++q) st[b].c[q] = c[q] / B.nv;
+      st[b].V = B.V0;
+    }
+    put(h->d_bstate, st.data(), sizeof(BeadState) * st.size());
+  }
   put(h->d_swimmers, h->swimmers.data(), sizeof(Swimmer) * h->swimmers.size());
   put(h->d_marker_bead, h->marker_bead.data(), sizeof(int) * nm);
   put(h->d_tri, tri.data(), sizeof(int) * tri.size());
@@ -330,10 +350,8 @@ int upload(lbm_handle* h) {
     }
     put(h->d_theta0, cs.data(), sizeof(double) * cs.size());
   }
-  put(h->d_vt_off, vt_off.data(), sizeof(int) * vt_off.size());
-  put(h->d_vt, vtf.data(), sizeof(int) * vtf.size());
-  put(h->d_vh_off, vh_off.data(), sizeof(int) * vh_off.size());
-  put(h->d_vh, vhf.data(), sizeof(int) * vhf.size());
+  put(h->d_lane_elem, lane_elem.data(), sizeof(int) * lane_elem.size());
+  put(h->d_lane_v, lane_v.data(), sizeof(int) * lane_v.size());
   put(h->d_spread_bead, spread_bead.data(), sizeof(int) * spread_bead.size());
   if (rc != LBM_OK) return rc;
 
@@ -357,10 +375,8 @@ int upload(lbm_handle* h) {
   d.th0cs = h->d_theta0;
   d.ntri = ntri;
   d.nh = nh;
-  d.vt_off = h->d_vt_off;
-  d.vt = h->d_vt;
-  d.vh_off = h->d_vh_off;
-  d.vh = h->d_vh;
+  d.lane_elem = h->d_lane_elem;
+  d.lane_v = reinterpret_cast<const int4*>(h->d_lane_v);
   d.spread_blocks = h->spread_blocks;
   d.spread_bead = h->d_spread_bead;
   d.near = h->d_near;
