@@ -20,6 +20,24 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+PMC_PROFILE = os.path.join(ROOT, "profiles", "stream_collide_128cubed_pmc.txt")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2202_12147_amd", "csrc", "lattice_kernels.hip")
+
+
+def measured_traffic():
+    """HBM bytes per full-grid stream-collide launch from the committed
+    rocprofv3 counter runs, or None when the kernel source has changed since."""
+    import hashlib
+    try:
+        fields = dict(line.split(": ", 1) for line in open(PMC_PROFILE).read().splitlines()
+                      if line and not line.startswith("#"))
+        src = open(KERNEL_SOURCE).read()
+    except OSError:
+        return None
+    dev = src[:src.index("}  // namespace")]
+    if hashlib.sha256(dev.encode()).hexdigest() != fields.get("kernel_source_sha256", "").strip():
+        return None
+    return int(fields["traffic_bytes_per_launch"])
 
 
 def cpu_baseline(case, budget_s=12.0):
@@ -88,6 +106,8 @@ def main():
     avg_ms = kms / max(launches, 1)
     achieved = lat.bytes_per_step / (avg_ms * 1e-3) / 1e9
     copy_gbs = lbmib.copy_bandwidth(1 << 30, 20)
+    tbytes = measured_traffic()
+    traffic = None if tbytes is None else round(tbytes / (avg_ms * 1e-3) / 1e9, 1)
 
     out = {
         "metric": "MLUPS & HBM GB/s of D3Q19+IBM step; adjoint/forward time ratio; batch MLUPS",
@@ -107,7 +127,8 @@ def main():
                    "grid": list(case["shape"]), "markers": lat.n_markers, "seed": 0,
                    "storage": "fp32 shifted"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
+                     "traffic_bytes_per_launch": tbytes,
                      "kernel": "k_stream_collide<fp32,256,all> (full grid, 19 loads + 19 stores per node)",
                      "avg_kernel_ms": round(avg_ms, 5), "launches_timed": launches,
                      "bytes_per_launch": lat.bytes_per_step,

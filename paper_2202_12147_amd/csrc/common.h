@@ -124,8 +124,10 @@ struct Dev {
 };
 
 // Launch wrappers (defined in the .hip files).
+// ev0 / ev1 (optional): events stamped by the launch's own dispatch packet
 void launch_stream_collide(const Dev& d, int storage, int mode, int block, int nblocks, int remap,
-                           int resident, int ncu, hipStream_t s);
+                           int resident, int ncu, hipStream_t s, hipEvent_t ev0 = nullptr,
+                           hipEvent_t ev1 = nullptr);
 void launch_tick(const Dev& d, int count, hipStream_t s);
 void launch_velocity(const Dev& d, int storage, int nblocks, float* u_out, float* rho_out,
                      hipStream_t s);

@@ -19,6 +19,8 @@
 
 #include "common.h"
 
+#include <hip/hip_ext.h>
+
 #include <algorithm>
 
 namespace lbmib {
@@ -376,38 +378,50 @@ void launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t s) {
                      static_cast<f32x4*>(dst), n);
 }
 
+// Launch through hipExtLaunchKernelGGL when timing: the start / stop events are
+// stamped by the kernel's own dispatch packet, so the elapsed time is the
+// kernel's duration without the cost of separate event packets.
+template <class K>
+static void launch_k(K kernel, int grid, int block, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, const Dev& d,
+                     int remap, int nblocks, int resident) {
+  if (ev0)
+    hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(block), 0, s, ev0, ev1, 0, d, remap, nblocks, resident);
+  else
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), 0, s, d, remap, nblocks, resident);
+}
+
 template <int ST, int MODE>
 static void launch_sc_mode(const Dev& d, int block, int nblocks, int remap, int resident, int ncu,
-                           hipStream_t s) {
+                           hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   int grid = remap ? (nblocks + 7) / 8 * 8 : nblocks;
   if (MODE == kScActive) grid = d.max_near;
   if (MODE == kScBulk && resident > 0) grid = std::min(grid, ncu * resident) / 8 * 8;
   if (MODE != kScBulk) resident = 0;
   if (block == 128)
-    hipLaunchKernelGGL((k_stream_collide<ST, 128, MODE>), dim3(grid), dim3(128), 0, s, d, remap, nblocks, resident);
+    launch_k(k_stream_collide<ST, 128, MODE>, grid, 128, s, ev0, ev1, d, remap, nblocks, resident);
   else if (block == 512)
-    hipLaunchKernelGGL((k_stream_collide<ST, 512, MODE>), dim3(grid), dim3(512), 0, s, d, remap, nblocks, resident);
+    launch_k(k_stream_collide<ST, 512, MODE>, grid, 512, s, ev0, ev1, d, remap, nblocks, resident);
   else
-    hipLaunchKernelGGL((k_stream_collide<ST, 256, MODE>), dim3(grid), dim3(256), 0, s, d, remap, nblocks, resident);
+    launch_k(k_stream_collide<ST, 256, MODE>, grid, 256, s, ev0, ev1, d, remap, nblocks, resident);
 }
 
 template <int ST>
 static void launch_sc_st(const Dev& d, int mode, int block, int nblocks, int remap, int resident,
-                         int ncu, hipStream_t s) {
+                         int ncu, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   if (mode == kScBulk)
-    launch_sc_mode<ST, kScBulk>(d, block, nblocks, remap, resident, ncu, s);
+    launch_sc_mode<ST, kScBulk>(d, block, nblocks, remap, resident, ncu, s, ev0, ev1);
   else if (mode == kScActive)
-    launch_sc_mode<ST, kScActive>(d, block, nblocks, remap, resident, ncu, s);
+    launch_sc_mode<ST, kScActive>(d, block, nblocks, remap, resident, ncu, s, ev0, ev1);
   else
-    launch_sc_mode<ST, kScAll>(d, block, nblocks, remap, resident, ncu, s);
+    launch_sc_mode<ST, kScAll>(d, block, nblocks, remap, resident, ncu, s, ev0, ev1);
 }
 
 void launch_stream_collide(const Dev& d, int storage, int mode, int block, int nblocks, int remap,
-                           int resident, int ncu, hipStream_t s) {
+                           int resident, int ncu, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   if (storage == kFp16)
-    launch_sc_st<kFp16>(d, mode, block, nblocks, remap, resident, ncu, s);
+    launch_sc_st<kFp16>(d, mode, block, nblocks, remap, resident, ncu, s, ev0, ev1);
   else
-    launch_sc_st<kFp32>(d, mode, block, nblocks, remap, resident, ncu, s);
+    launch_sc_st<kFp32>(d, mode, block, nblocks, remap, resident, ncu, s, ev0, ev1);
 }
 
 void launch_tick(const Dev& d, int count, hipStream_t s) {

@@ -398,15 +398,19 @@ int upload(lbm_handle* h) {
   return LBM_OK;
 }
 
-void timing_event(lbm_handle* h) {
-  if (h->ev_used + 1 > h->ev_pool.size()) {
+// Two timing events for one launch (nullptr when timing is off).
+void timing_pair(lbm_handle* h, hipEvent_t* e0, hipEvent_t* e1) {
+  *e0 = *e1 = nullptr;
+  if (!h->timing) return;
+  if (h->ev_used + 2 > h->ev_pool.size()) {
     for (int i = 0; i < 64; ++i) {
       hipEvent_t e;
       (void)hipEventCreate(&e);
       h->ev_pool.push_back(e);
     }
   }
-  (void)hipEventRecord(h->ev_pool[h->ev_used++], h->stream);
+  *e0 = h->ev_pool[h->ev_used++];
+  *e1 = h->ev_pool[h->ev_used++];
 }
 
 // Enqueue `count` steps.  Without swimmers each step is one full-grid
@@ -421,9 +425,10 @@ void enqueue_steps(lbm_handle* h, int64_t count) {
   if (h->swimmers.empty()) {
     for (int64_t i = 0; i < count; ++i) {
       d.sub = (int)i;
-      if (h->timing) timing_event(h);
-      launch_stream_collide(d, h->storage, kLaunchAll, h->sc_block, h->sc_blocks, h->sc_remap, 0, h->ncu, h->stream);
-      if (h->timing) timing_event(h);
+      hipEvent_t e0, e1;
+      timing_pair(h, &e0, &e1);
+      launch_stream_collide(d, h->storage, kLaunchAll, h->sc_block, h->sc_blocks, h->sc_remap, 0, h->ncu, h->stream,
+                            e0, e1);
     }
     launch_tick(d, (int)count, h->stream);
     return;
@@ -435,9 +440,10 @@ void enqueue_steps(lbm_handle* h, int64_t count) {
       launch_bead_stats(d, 0, h->stream);
       launch_vertex_forces(d, h->stream);
       launch_spread(d, h->stream);
-      if (h->timing) timing_event(h);
-      launch_stream_collide(d, h->storage, kLaunchAll, h->sc_block, h->sc_blocks, h->sc_remap, 0, h->ncu, h->stream);
-      if (h->timing) timing_event(h);
+      hipEvent_t e0, e1;
+      timing_pair(h, &e0, &e1);
+      launch_stream_collide(d, h->storage, kLaunchAll, h->sc_block, h->sc_blocks, h->sc_remap, 0, h->ncu, h->stream,
+                            e0, e1);
       d.sub = (int)i + 1;
       launch_interp_advance(d, h->stream);
     }
@@ -454,14 +460,13 @@ void enqueue_steps(lbm_handle* h, int64_t count) {
     launch_vertex_forces(d, h->side);
     launch_spread(d, h->side);
     (void)hipEventRecord(join, h->side);
-    if (h->timing) timing_event(h);
+    hipEvent_t e0, e1;
+    timing_pair(h, &e0, &e1);
     launch_stream_collide(d, h->storage, kLaunchBulk, h->sc_block, h->sc_blocks, h->sc_remap, h->sc_resident,
-                          h->ncu, h->stream);
-    if (h->timing) timing_event(h);
+                          h->ncu, h->stream, e0, e1);
     (void)hipStreamWaitEvent(h->stream, join, 0);
-    if (h->timing) timing_event(h);
-    launch_stream_collide(d, h->storage, kLaunchActive, h->sc_block, h->sc_blocks, 0, 0, h->ncu, h->stream);
-    if (h->timing) timing_event(h);
+    timing_pair(h, &e0, &e1);
+    launch_stream_collide(d, h->storage, kLaunchActive, h->sc_block, h->sc_blocks, 0, 0, h->ncu, h->stream, e0, e1);
   }
   d.sub = (int)count;
   launch_interp_advance(d, h->stream);
