@@ -59,6 +59,44 @@ def cpu_baseline(case, budget_s=12.0):
             "sample": f"{steps} FP64 steps of the same 128^3 swimmer workload (IBM included)"}
 
 
+def fp16_section(lbmib, wl, case, steps, warmup, gmax):
+    """FP16-shifted storage on the same workload and GPU: throughput, kernel
+    bandwidth (76 B per node), and the small case's swimmer displacement
+    against the FP32 run on the same GPU (FP32 itself is pinned to the FP64
+    oracle by the tests)."""
+    import numpy as np
+    S = lbmib.fp16_scale_for(gmax)
+    nodes = case["shape"][0] * case["shape"][1] * case["shape"][2]
+    lat = lbmib.from_workload(case, storage=lbmib.FP16_SHIFTED, fp16_scale=S)
+    lat.step(warmup)
+    lat.sync()
+    t0 = time.perf_counter()
+    lat.step(steps)
+    lat.sync()
+    dt = time.perf_counter() - t0
+    lat.set_stream_collide_launch(256, True, -1)
+    lat.step(20)
+    lat.set_kernel_timing(True)
+    lat.step(min(steps, 2000))
+    kms, n = lat.kernel_time()
+    lat.set_kernel_timing(False)
+    lat.sync()
+    gbs = lat.bytes_per_step / (kms / n * 1e-3) / 1e9
+    small = wl.small_case()
+    disp = {}
+    for name, st, sc in (("fp32", lbmib.FP32_SHIFTED, 1.0), ("fp16", lbmib.FP16_SHIFTED, 2.0 ** 27)):
+        g = lbmib.from_workload(small, storage=st, fp16_scale=sc)
+        x0 = g.swimmer_centres()[0, 0]
+        g.step(small["steps"])
+        disp[name] = g.swimmer_centres()[0, 0] - x0
+    return {"storage": f"fp16 shifted, S=2^{int(np.log2(S))}", "value": round(nodes * steps / dt / 1e6, 1),
+            "unit": "MLUPS", "ms_per_step": round(dt / steps * 1e3, 5),
+            "kernel_gbs": round(gbs, 1), "kernel_frac": round(gbs / PEAK_HBM_GBS, 4),
+            "bytes_per_launch": lat.bytes_per_step,
+            "small_case_displacement": {"fp32": disp["fp32"], "fp16": disp["fp16"],
+                                        "rel_diff": abs(disp["fp16"] - disp["fp32"]) / abs(disp["fp32"])}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -135,6 +173,10 @@ def main():
                      "copy_probe_gbs": round(copy_gbs, 1),
                      "frac_of_copy_probe": round(achieved / copy_gbs, 4)},
     }
+    lat.set_stream_collide_launch(256, True, 0)
+    import numpy as np
+    gmax = float(np.abs(lat.populations()).max())
+    out["fp16"] = fp16_section(lbmib, wl, case, args.steps, args.warmup, gmax)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(case)
     print(json.dumps(out), flush=True)

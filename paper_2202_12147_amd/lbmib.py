@@ -311,6 +311,12 @@ class Lattice:
         return self.lib.lbm_bytes_per_step(self.h)
 
 
+def fp16_scale_for(max_abs_dev, headroom=16.0):
+    """Power-of-two scale S for FP16-shifted storage that puts the largest
+    expected |f - w| a factor `headroom` below the half-precision maximum."""
+    return 2.0 ** math.floor(math.log2(65504.0 / headroom / float(max_abs_dev)))
+
+
 def copy_bandwidth(nbytes=1 << 30, iters=20):
     """Achievable device-memory bandwidth (GB/s, read + write) of a plain copy."""
     lib = load_library()
