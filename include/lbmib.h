@@ -173,9 +173,49 @@ int lbm_get_density(lbm_handle* h, float* dst, int on_device);
 int lbm_get_conserved(lbm_handle* h, double out[4]);
 
 /* Population deviations g = f* - w of the current post-collision state,
- * host float64 [19][nz][ny][nx].  set: before the first step only. */
+ * host float64 [19][nz][ny][nx] (for a batch, box after box, each
+ * [19][nz][ny][nx]).  set: before the first step only. */
 int lbm_set_populations(lbm_handle* h, const double* dev);
 int lbm_get_populations(lbm_handle* h, double* dev);
+
+/* ---- batches of independent boxes -------------------------------------------- */
+/* One periodic box of a batch: its own grid, relaxation time and forcing. */
+typedef struct {
+  lbm_grid grid;
+  double tau;
+  int32_t forcing; /* lbm_forcing */
+} lbm_box_desc;
+
+/* Create a handle stepping `nboxes` independent periodic boxes together: every
+ * step is one pass of the method over all boxes (shared launches, one graph).
+ * Each box starts at rest.  Box b's nodes follow box b-1's in the population
+ * planes.  Validation as lbm_create per box.  lbm_step, lbm_sync,
+ * lbm_get_swimmer_centres, lbm_get_bead_centres, lbm_get_markers and the
+ * checkpoint calls act on the whole batch; swimmers are numbered across boxes
+ * in the order they were added.  Errors: as lbm_create. */
+int lbm_batch_create(const lbm_box_desc* boxes, int32_t nboxes, const lbm_opts* opts,
+                     lbm_handle** out);
+/* Add a swimmer (as lbm_swimmer_add) to box `box`.  Swimmers must be added in
+ * non-decreasing box order (LBM_EINVAL otherwise). */
+int lbm_batch_swimmer_add(lbm_handle* h, int32_t box, const lbm_bead_desc beads[3],
+                          const lbm_spring_desc springs[2], const lbm_actuation_desc* act,
+                          int32_t* id);
+int32_t lbm_n_boxes(const lbm_handle* h);
+/* Velocity (layout as lbm_get_velocity) of one box of the batch. */
+int lbm_batch_get_velocity(lbm_handle* h, int32_t box, float* dst, int on_device);
+/* Conserved sums (as lbm_get_conserved) of one box; box = -1 sums all boxes. */
+int lbm_batch_get_conserved(lbm_handle* h, int32_t box, double out[4]);
+
+/* Autotuner for the stream-collide launch shape (see
+ * lbm_set_stream_collide_launch): times every candidate shape over
+ * `steps_per_candidate` steps from a device snapshot of the state, restores
+ * the state afterwards (the simulation does not advance) and keeps the
+ * fastest shape.  With `cache_path` non-NULL the winner is looked up in and
+ * appended to that text file, keyed by the handle's geometry.  `report`
+ * (optional, `report_len` bytes) receives one line per candidate.
+ * Errors: LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EIO. */
+int lbm_autotune(lbm_handle* h, int32_t steps_per_candidate, const char* cache_path, char* report,
+                 int32_t report_len);
 
 /* ---- checkpoint ---------------------------------------------------------------- */
 /* Write / restore the full dynamic state (populations, forces, tile stamps,

@@ -131,7 +131,7 @@ void launch_stream_collide(const Dev& d, int storage, int mode, int block, int n
 void launch_tick(const Dev& d, int count, hipStream_t s);
 void launch_velocity(const Dev& d, int storage, int nblocks, float* u_out, float* rho_out,
                      hipStream_t s);
-void launch_conserved(const Dev& d, int storage, double* partial, int nparts, double* out,
+void launch_conserved(const Dev& d, int storage, int box, double* partial, int nparts, double* out,
                       hipStream_t s);
 void launch_bead_stats(const Dev& d, int mark_offset, hipStream_t s);
 void launch_vertex_forces(const Dev& d, hipStream_t s);

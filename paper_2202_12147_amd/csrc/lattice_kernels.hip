@@ -260,17 +260,15 @@ __global__ __launch_bounds__(kScBlock) void k_velocity(Dev d, float* __restrict_
   const int id = (blk - B.block0) * kScBlock + (int)threadIdx.x;
   if (id >= B.n) return;
   const int64_t c = *d.step;
-  // output planes are packed: total nodes of all boxes, box offset node0
-  // relative to the first box
-  const int64_t tot = d.boxes[d.nboxes - 1].node0 + d.boxes[d.nboxes - 1].n - d.boxes[0].node0;
-  const int64_t ob = B.node0 - d.boxes[0].node0 + id;
+  // outputs box after box: velocity [box][3][n_box], density [box][n_box]
+  const int64_t ob = 3 * B.node0 + id, nb = B.n, orho = B.node0 + id;
   if (c == 0) {
     if (uo) {
       uo[ob] = 0.0f;
-      uo[tot + ob] = 0.0f;
-      uo[2 * tot + ob] = 0.0f;
+      uo[nb + ob] = 0.0f;
+      uo[2 * nb + ob] = 0.0f;
     }
-    if (ro) ro[ob] = 1.0f;
+    if (ro) ro[orho] = 1.0f;
     return;
   }
   const int64_t n = c - 1;
@@ -296,10 +294,10 @@ __global__ __launch_bounds__(kScBlock) void k_velocity(Dev d, float* __restrict_
   const float ir = 1.0f / m.rho;
   if (uo) {
     uo[ob] = (m.jx + 0.5f * Fx) * ir;
-    uo[tot + ob] = (m.jy + 0.5f * Fy) * ir;
-    uo[2 * tot + ob] = (m.jz + 0.5f * Fz) * ir;
+    uo[nb + ob] = (m.jy + 0.5f * Fy) * ir;
+    uo[2 * nb + ob] = (m.jz + 0.5f * Fz) * ir;
   }
-  if (ro) ro[ob] = m.rho;
+  if (ro) ro[orho] = m.rho;
 }
 
 // Block sum of 4 doubles through wavefront shuffles, result in thread 0.
@@ -323,7 +321,7 @@ __device__ inline void block_sum4(double* v) {
 
 // Stage 1: per-block FP64 sums of g and g c over the current state.
 template <int ST>
-__global__ __launch_bounds__(kScBlock) void k_conserved_partial(Dev d, double* __restrict__ part) {
+__global__ __launch_bounds__(kScBlock) void k_conserved_partial(Dev d, int box, double* __restrict__ part) {
   using IO = PopIO<ST>;
   using T = typename IO::T;
   const int64_t c = *d.step;
@@ -331,6 +329,7 @@ __global__ __launch_bounds__(kScBlock) void k_conserved_partial(Dev d, double* _
   const int64_t ps = d.pstride;
   double v[4] = {0, 0, 0, 0};
   for (int b = 0; b < d.nboxes; ++b) {
+    if (box >= 0 && b != box) continue;
     const Box B = d.boxes[b];
     for (int64_t id = (int64_t)blockIdx.x * kScBlock + threadIdx.x; id < B.n;
          id += (int64_t)gridDim.x * kScBlock) {
@@ -436,12 +435,12 @@ void launch_velocity(const Dev& d, int storage, int nblocks, float* u_out, float
     hipLaunchKernelGGL(k_velocity<kFp32>, dim3(nblocks), dim3(kScBlock), 0, s, d, u_out, rho_out);
 }
 
-void launch_conserved(const Dev& d, int storage, double* partial, int nparts, double* out,
+void launch_conserved(const Dev& d, int storage, int box, double* partial, int nparts, double* out,
                       hipStream_t s) {
   if (storage == kFp16)
-    hipLaunchKernelGGL(k_conserved_partial<kFp16>, dim3(nparts), dim3(kScBlock), 0, s, d, partial);
+    hipLaunchKernelGGL(k_conserved_partial<kFp16>, dim3(nparts), dim3(kScBlock), 0, s, d, box, partial);
   else
-    hipLaunchKernelGGL(k_conserved_partial<kFp32>, dim3(nparts), dim3(kScBlock), 0, s, d, partial);
+    hipLaunchKernelGGL(k_conserved_partial<kFp32>, dim3(nparts), dim3(kScBlock), 0, s, d, box, partial);
   hipLaunchKernelGGL(k_conserved_final, dim3(1), dim3(kScBlock), 0, s, partial, nparts, out);
 }
 

@@ -117,9 +117,7 @@ struct lbm_handle {
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
-  lbm_grid grid{};
-  double tau = 1.0;
-  int forcing = LBM_GUO, storage = LBM_FP32_SHIFTED, width = 3;
+  int storage = LBM_FP32_SHIFTED, width = 3;
   float fp16_scale = 1.0f;
   bool use_graphs = true;
   std::string err;
@@ -147,7 +145,10 @@ struct lbm_handle {
   float *F = nullptr, *u = nullptr, *uout = nullptr;
   int* stamp = nullptr;
   Box* d_boxes = nullptr;
-  int* d_block_box = nullptr;
+  int* d_block_box = nullptr;     // 256-node block -> box
+  int* d_sc_block_box = nullptr;  // stream-collide block -> box (sized for block 128)
+  int* d_sc_box_block0 = nullptr; // first stream-collide block of each box
+  int64_t sc_table_cap = 0;
   int64_t* d_step = nullptr;
   double* d_pos = nullptr;
   float *d_U = nullptr, *d_fm = nullptr;
@@ -204,6 +205,61 @@ int reserved_tiles(double radius, int width, int T) {
   return std::min(T, (span + kTile - 2) / kTile + 1);
 }
 
+// Host layout of population deviations: box after box, each [19][n_box];
+// device layout [q][node] with box b's nodes starting at node0_b.
+template <class F>
+void for_each_population(const lbm_handle* h, F f) {
+  for (const Box& B : h->boxes) {
+    const int64_t hoff = kQ * B.node0;
+    for (int q = 0; q < kQ; ++q)
+      for (int64_t n = 0; n < B.n; ++n) f(hoff + q * B.n + n, q * h->pstride + B.node0 + n);
+  }
+}
+
+// Geometry signature of a handle (FNV-1a over box shapes, relaxation times,
+// forcing, storage, kernel width and markers): keys checkpoints and the tuner
+// cache.
+uint64_t signature(const lbm_handle* h) {
+  uint64_t x = 1469598103934665603ull;
+  auto mix = [&](const void* p, size_t n) {
+    const unsigned char* c = static_cast<const unsigned char*>(p);
+    for (size_t i = 0; i < n; ++i) x = (x ^ c[i]) * 1099511628211ull;
+  };
+  for (const Box& B : h->boxes) {
+    const int dims[4] = {B.nx, B.ny, B.nz, B.forcing};
+    mix(dims, sizeof dims);
+    mix(&B.tau, sizeof B.tau);
+  }
+  const int rest[3] = {h->storage, h->width, h->nm};
+  mix(rest, sizeof rest);
+  return x;
+}
+
+// Stream-collide block tables for the current block size: first block of each
+// box and block -> box (device copies used only when there are several boxes).
+int build_sc_tables(lbm_handle* h) {
+  std::vector<int> first(h->boxes.size()), owner;
+  int blocks = 0;
+  for (size_t b = 0; b < h->boxes.size(); ++b) {
+    first[b] = blocks;
+    const int nb = (int)((h->boxes[b].n + h->sc_block - 1) / h->sc_block);
+    owner.insert(owner.end(), nb, (int)b);
+    blocks += nb;
+  }
+  h->sc_blocks = blocks;
+  if (h->boxes.size() > 1) {
+    if ((int64_t)owner.size() > h->sc_table_cap) return h->fail(LBM_EINVAL, "block table too small");
+    int rc = h->hip(hipMemcpy(h->d_sc_block_box, owner.data(), sizeof(int) * owner.size(), hipMemcpyHostToDevice),
+                    "hipMemcpy");
+    if (!rc) rc = h->hip(hipMemcpy(h->d_sc_box_block0, first.data(), sizeof(int) * first.size(),
+                                   hipMemcpyHostToDevice), "hipMemcpy");
+    if (rc) return rc;
+  }
+  h->dev.sc_block_box = h->d_sc_block_box;
+  h->dev.sc_box_block0 = h->d_sc_box_block0;
+  return LBM_OK;
+}
+
 // Stream-collide block geometry and the bound on near blocks: per bead the
 // marked node box is its reserved tile span plus two nodes each side.
 void set_near_bounds(lbm_handle* h) {
@@ -211,8 +267,8 @@ void set_near_bounds(lbm_handle* h) {
   d.nsc = h->sc_blocks;
   d.sc_bs = h->sc_block;
   int64_t mx = 0;
-  const Box& B = h->boxes[0];
   for (const Bead& b : h->beads) {
+    const Box& B = h->boxes[b.box];
     const int64_t sx = std::min<int64_t>(b.tiles_x * kTile + 4, B.nx);
     const int64_t sy = std::min<int64_t>(b.tiles_y * kTile + 4, B.ny);
     const int64_t sz = std::min<int64_t>(b.tiles_z * kTile + 4, B.nz);
@@ -283,8 +339,15 @@ int upload(lbm_handle* h) {
     spread_bead.insert(spread_bead.end(), cnt, (int)b);
   }
   h->spread_blocks = (int)spread_bead.size();
-  h->boxes[0].bead0 = 0;
-  h->boxes[0].nbeads = (int)h->beads.size();
+  for (Box& B : h->boxes) {
+    B.bead0 = 0;
+    B.nbeads = 0;
+  }
+  for (size_t b = 0; b < h->beads.size(); ++b) {
+    Box& B = h->boxes[h->beads[b].box];
+    if (B.nbeads == 0) B.bead0 = (int)b;
+    B.nbeads += 1;
+  }
 
   auto put = [&](void* dst, const void* src, size_t bytes) {
     if (rc != LBM_OK || bytes == 0) return;
@@ -537,14 +600,23 @@ const char* lbm_strerror(int code) {
 
 const char* lbm_last_error(const lbm_handle* h) { return h ? h->err.c_str() : "null handle"; }
 
-int lbm_create(const lbm_grid* grid, double tau, int forcing, const lbm_opts* opts,
-               lbm_handle** out) {
-  if (!out || !grid) return LBM_EINVAL;
+}  // extern "C"
+
+namespace {
+
+int create_boxes(const lbm_box_desc* boxes, int nboxes, const lbm_opts* opts, lbm_handle** out) {
+  if (!out || !boxes || nboxes < 1) return LBM_EINVAL;
   *out = nullptr;
-  if (!(tau > 0.5) || !std::isfinite(tau)) return LBM_EINVAL;
-  if (grid->nx < 16 || grid->ny < 16 || grid->nz < 16) return LBM_EINVAL;
-  if ((int64_t)grid->nx * grid->ny * grid->nz >= (int64_t)1 << 31) return LBM_EINVAL;
-  if (forcing != LBM_GUO && forcing != LBM_SHAN_CHEN) return LBM_EINVAL;
+  int64_t total = 0;
+  for (int b = 0; b < nboxes; ++b) {
+    const lbm_box_desc& d = boxes[b];
+    if (!(d.tau > 0.5) || !std::isfinite(d.tau)) return LBM_EINVAL;
+    if (d.grid.nx < 16 || d.grid.ny < 16 || d.grid.nz < 16) return LBM_EINVAL;
+    if ((int64_t)d.grid.nx * d.grid.ny * d.grid.nz >= (int64_t)1 << 31) return LBM_EINVAL;
+    if (d.forcing != LBM_GUO && d.forcing != LBM_SHAN_CHEN) return LBM_EINVAL;
+    total += (int64_t)d.grid.nx * d.grid.ny * d.grid.nz;
+  }
+  if (total >= (int64_t)1 << 31) return LBM_EINVAL;
   lbm_opts o{LBM_FP32_SHIFTED, 3, 1.0f, 1, nullptr};
   if (opts) o = *opts;
   if (o.storage != LBM_FP32_SHIFTED && o.storage != LBM_FP16_SHIFTED) return LBM_EINVAL;
@@ -556,9 +628,6 @@ int lbm_create(const lbm_grid* grid, double tau, int forcing, const lbm_opts* op
     if (!(o.fp16_scale > 0.0f) || std::ldexp(1.0, e - 1) != o.fp16_scale) return LBM_EINVAL;
   }
   auto* h = new lbm_handle();
-  h->grid = *grid;
-  h->tau = tau;
-  h->forcing = forcing;
   h->storage = o.storage;
   h->width = o.delta_width;
   h->fp16_scale = o.fp16_scale;
@@ -580,26 +649,39 @@ int lbm_create(const lbm_grid* grid, double tau, int forcing, const lbm_opts* op
     }
     h->own_stream = true;
   }
-  Box B{};
-  B.nx = grid->nx;
-  B.ny = grid->ny;
-  B.nz = grid->nz;
-  B.tx = (B.nx + kTile - 1) / kTile;
-  B.ty = (B.ny + kTile - 1) / kTile;
-  B.tz = (B.nz + kTile - 1) / kTile;
-  B.node0 = 0;
-  B.n = (int64_t)B.nx * B.ny * B.nz;
-  B.tile0 = 0;
-  B.block0 = 0;
-  B.forcing = forcing;
-  B.tau = (float)tau;
-  B.omega = (float)(1.0 / tau);
-  h->boxes.push_back(B);
-  h->nodes = B.n;
-  h->pstride = (B.n + 127) / 128 * 128;
-  h->ntiles = B.tx * B.ty * B.tz;
-  h->out_blocks = (int)((B.n + kScBlock - 1) / kScBlock);
-  h->sc_blocks = (int)((B.n + h->sc_block - 1) / h->sc_block);
+  int64_t node0 = 0;
+  int tile0 = 0, block0 = 0;
+  int64_t sc_cap = 0;
+  std::vector<int> block_box;
+  for (int b = 0; b < nboxes; ++b) {
+    const lbm_box_desc& d = boxes[b];
+    Box B{};
+    B.nx = d.grid.nx;
+    B.ny = d.grid.ny;
+    B.nz = d.grid.nz;
+    B.tx = (B.nx + kTile - 1) / kTile;
+    B.ty = (B.ny + kTile - 1) / kTile;
+    B.tz = (B.nz + kTile - 1) / kTile;
+    B.node0 = node0;
+    B.n = (int64_t)B.nx * B.ny * B.nz;
+    B.tile0 = tile0;
+    B.block0 = block0;
+    B.forcing = d.forcing;
+    B.tau = (float)d.tau;
+    B.omega = (float)(1.0 / d.tau);
+    const int nb = (int)((B.n + kScBlock - 1) / kScBlock);
+    block_box.insert(block_box.end(), nb, b);
+    node0 += B.n;
+    tile0 += B.tx * B.ty * B.tz;
+    block0 += nb;
+    sc_cap += (B.n + 127) / 128;
+    h->boxes.push_back(B);
+  }
+  h->nodes = node0;
+  h->pstride = (node0 + 127) / 128 * 128;
+  h->ntiles = tile0;
+  h->out_blocks = block0;
+  h->sc_table_cap = sc_cap;
 
   const size_t eb = element_bytes(h);
   h->pop[0] = h->alloc<char>(eb * kQ * h->pstride, rc);
@@ -607,11 +689,16 @@ int lbm_create(const lbm_grid* grid, double tau, int forcing, const lbm_opts* op
   h->F = h->alloc<float>(3 * h->pstride, rc);
   h->u = h->alloc<float>(3 * h->pstride, rc);
   h->stamp = h->alloc<int>(h->ntiles, rc);
-  h->d_boxes = h->alloc<Box>(1, rc);
+  h->d_boxes = h->alloc<Box>(nboxes, rc);
   h->d_step = h->alloc<int64_t>(1, rc);
   h->d_overflow = h->alloc<int>(1, rc);
   h->d_partial = h->alloc<double>(4 * kReduceParts, rc);
   h->d_out = h->alloc<double>(4, rc);
+  if (nboxes > 1) {
+    h->d_block_box = h->alloc<int>(block_box.size(), rc);
+    h->d_sc_block_box = h->alloc<int>(sc_cap, rc);
+    h->d_sc_box_block0 = h->alloc<int>(nboxes, rc);
+  }
   if (rc) {
     lbm_destroy(h);
     return LBM_ENOMEM;
@@ -623,7 +710,12 @@ int lbm_create(const lbm_grid* grid, double tau, int forcing, const lbm_opts* op
   if (!rc) rc = h->hip(hipMemset(h->stamp, 0x80, sizeof(int) * h->ntiles), "hipMemset");
   if (!rc) rc = h->hip(hipMemset(h->d_step, 0, sizeof(int64_t)), "hipMemset");
   if (!rc) rc = h->hip(hipMemset(h->d_overflow, 0, sizeof(int)), "hipMemset");
-  if (!rc) rc = h->hip(hipMemcpy(h->d_boxes, h->boxes.data(), sizeof(Box), hipMemcpyHostToDevice), "hipMemcpy");
+  if (!rc) rc = h->hip(hipMemcpy(h->d_boxes, h->boxes.data(), sizeof(Box) * nboxes, hipMemcpyHostToDevice),
+                       "hipMemcpy");
+  if (!rc && nboxes > 1)
+    rc = h->hip(hipMemcpy(h->d_block_box, block_box.data(), sizeof(int) * block_box.size(), hipMemcpyHostToDevice),
+                "hipMemcpy");
+  if (!rc) rc = build_sc_tables(h);
   if (!rc) rc = h->hip(hipDeviceSynchronize(), "hipDeviceSynchronize");
   if (rc) {
     lbm_destroy(h);
@@ -637,8 +729,8 @@ int lbm_create(const lbm_grid* grid, double tau, int forcing, const lbm_opts* op
   d.u = h->u;
   d.stamp = h->stamp;
   d.boxes = h->d_boxes;
-  d.nboxes = 1;
-  d.block_box = nullptr;
+  d.nboxes = nboxes;
+  d.block_box = h->d_block_box;
   d.step = h->d_step;
   d.sub = 0;
   d.fp16_scale = h->fp16_scale;
@@ -648,6 +740,23 @@ int lbm_create(const lbm_grid* grid, double tau, int forcing, const lbm_opts* op
   *out = h;
   return LBM_OK;
 }
+
+}  // namespace
+
+extern "C" {
+
+int lbm_create(const lbm_grid* grid, double tau, int forcing, const lbm_opts* opts,
+               lbm_handle** out) {
+  if (!grid) return LBM_EINVAL;
+  lbm_box_desc b{*grid, tau, forcing};
+  return create_boxes(&b, 1, opts, out);
+}
+
+int lbm_batch_create(const lbm_box_desc* boxes, int32_t nboxes, const lbm_opts* opts, lbm_handle** out) {
+  return create_boxes(boxes, nboxes, opts, out);
+}
+
+int32_t lbm_n_boxes(const lbm_handle* h) { return h ? (int32_t)h->boxes.size() : -1; }
 
 int lbm_destroy(lbm_handle* h) {
   if (!h) return LBM_OK;
@@ -665,10 +774,19 @@ int lbm_destroy(lbm_handle* h) {
 
 int lbm_swimmer_add(lbm_handle* h, const lbm_bead_desc beads[3], const lbm_spring_desc springs[2],
                     const lbm_actuation_desc* act, int32_t* id) {
+  return lbm_batch_swimmer_add(h, 0, beads, springs, act, id);
+}
+
+int lbm_batch_swimmer_add(lbm_handle* h, int32_t box, const lbm_bead_desc beads[3],
+                          const lbm_spring_desc springs[2], const lbm_actuation_desc* act, int32_t* id) {
   if (!h || !beads || !springs || !act) return LBM_EINVAL;
+  if (box < 0 || box >= (int)h->boxes.size()) return h->fail(LBM_EINVAL, "box index out of range");
+  if (!h->beads.empty() && h->beads.back().box > box)
+    return h->fail(LBM_EINVAL, "swimmers must be added in non-decreasing box order");
   if (h->stepped || h->uploaded) return h->fail(LBM_ESTATE, "swimmers must be added before the first step");
   if (!(act->period > 0)) return h->fail(LBM_EINVAL, "actuation period must be positive");
-  const int minedge = std::min(h->grid.nx, std::min(h->grid.ny, h->grid.nz));
+  const Box& BX = h->boxes[box];
+  const int minedge = std::min(BX.nx, std::min(BX.ny, BX.nz));
   for (int k = 0; k < 3; ++k) {
     if (!(beads[k].radius > 0) || beads[k].level < 0 || beads[k].level > 5)
       return h->fail(LBM_EINVAL, "bead radius must be positive and level in 0..5");
@@ -677,7 +795,7 @@ int lbm_swimmer_add(lbm_handle* h, const lbm_bead_desc beads[3], const lbm_sprin
   }
   Swimmer S{};
   const int sw = (int)h->swimmers.size();
-  const Box& B = h->boxes[0];
+  const Box& B = h->boxes[box];
   for (int k = 0; k < 3; ++k) {
     const lbm_bead_desc& bd = beads[k];
     const Mesh M = icosphere(bd.level);
@@ -687,7 +805,7 @@ int lbm_swimmer_add(lbm_handle* h, const lbm_bead_desc beads[3], const lbm_sprin
     b.nv = nv;
     b.tri0 = (int)h->tri.size() / 3;
     b.ntri = nt;
-    b.box = 0;
+    b.box = box;
     b.swimmer = sw;
     b.slot = k;
     b.tiles_x = reserved_tiles(bd.radius, h->width, B.tx);
@@ -895,13 +1013,16 @@ int lbm_get_marker_forces(lbm_handle* h, double* out) {
   return get_marker_f32(h, h->d_fm, out);
 }
 
-static int get_macro(lbm_handle* h, float* dst, int on_device, bool vel) {
+static int get_macro(lbm_handle* h, int box, float* dst, int on_device, bool vel) {
   if (!h || !dst) return LBM_EINVAL;
+  if (box < 0 || box >= (int)h->boxes.size()) return h->fail(LBM_EINVAL, "box index out of range");
+  const Box& B = h->boxes[box];
   const size_t comps = vel ? 3 : 1;
-  const size_t bytes = sizeof(float) * comps * h->nodes;
-  float* target = dst;
+  const size_t bytes = sizeof(float) * comps * B.n;
   int rc = LBM_OK;
-  if (!on_device) {
+  float* target = dst;
+  const bool direct = on_device && h->boxes.size() == 1;
+  if (!direct) {
     if (!h->uout) {
       h->uout = h->alloc<float>(3 * h->nodes, rc);
       if (rc) return h->fail(rc, "velocity staging allocation failed");
@@ -912,24 +1033,32 @@ static int get_macro(lbm_handle* h, float* dst, int on_device, bool vel) {
                   h->stream);
   rc = h->hip(hipGetLastError(), "k_velocity launch");
   if (rc) return rc;
-  if (!on_device) {
-    rc = h->hip(hipMemcpyAsync(dst, target, bytes, hipMemcpyDeviceToHost, h->stream), "hipMemcpyAsync");
+  if (!direct) {
+    const float* src = target + comps * B.node0;
+    rc = h->hip(hipMemcpyAsync(dst, src, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                               h->stream), "hipMemcpyAsync");
     if (rc) return rc;
   }
   return h->hip(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
 }
 
-int lbm_get_velocity(lbm_handle* h, float* dst, int on_device) { return get_macro(h, dst, on_device, true); }
-int lbm_get_density(lbm_handle* h, float* dst, int on_device) { return get_macro(h, dst, on_device, false); }
+int lbm_get_velocity(lbm_handle* h, float* dst, int on_device) { return get_macro(h, 0, dst, on_device, true); }
+int lbm_get_density(lbm_handle* h, float* dst, int on_device) { return get_macro(h, 0, dst, on_device, false); }
+int lbm_batch_get_velocity(lbm_handle* h, int32_t box, float* dst, int on_device) {
+  return get_macro(h, box, dst, on_device, true);
+}
 
-int lbm_get_conserved(lbm_handle* h, double out[4]) {
+int lbm_get_conserved(lbm_handle* h, double out[4]) { return lbm_batch_get_conserved(h, -1, out); }
+
+int lbm_batch_get_conserved(lbm_handle* h, int32_t box, double out[4]) {
   if (!h || !out) return LBM_EINVAL;
-  launch_conserved(h->dev, h->storage, h->d_partial, kReduceParts, h->d_out, h->stream);
+  if (box < -1 || box >= (int)h->boxes.size()) return h->fail(LBM_EINVAL, "box index out of range");
+  launch_conserved(h->dev, h->storage, box, h->d_partial, kReduceParts, h->d_out, h->stream);
   int rc = h->hip(hipMemcpyAsync(out, h->d_out, sizeof(double) * 4, hipMemcpyDeviceToHost, h->stream),
                   "hipMemcpyAsync");
   if (!rc) rc = h->hip(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
   if (rc) return rc;
-  out[0] += (double)h->nodes;  // sum of the weights: one per node
+  out[0] += (double)(box < 0 ? h->nodes : h->boxes[box].n);  // sum of the weights: one per node
   for (int k = 0; k < 4; ++k)
     if (!std::isfinite(out[k])) return h->fail(LBM_ENONFINITE, "non-finite mass or momentum");
   return LBM_OK;
@@ -938,18 +1067,16 @@ int lbm_get_conserved(lbm_handle* h, double out[4]) {
 int lbm_set_populations(lbm_handle* h, const double* dev) {
   if (!h || !dev) return LBM_EINVAL;
   if (h->stepped) return h->fail(LBM_ESTATE, "populations can only be set before the first step");
-  const int64_t N = h->nodes;
   const int cur = 0;  // step counter is 0 before stepping
   if (h->storage == LBM_FP16_SHIFTED) {
     std::vector<_Float16> buf(kQ * (size_t)h->pstride, (_Float16)0);
-    for (int q = 0; q < kQ; ++q)
-      for (int64_t n = 0; n < N; ++n)
-        buf[q * h->pstride + n] = (_Float16)((float)dev[q * N + n] * h->fp16_scale);
+    for_each_population(h, [&](int64_t hi, int64_t di) {
+      buf[di] = (_Float16)((float)dev[hi] * h->fp16_scale);
+    });
     return h->hip(hipMemcpy(h->pop[cur], buf.data(), buf.size() * 2, hipMemcpyHostToDevice), "hipMemcpy");
   }
   std::vector<float> buf(kQ * (size_t)h->pstride, 0.0f);
-  for (int q = 0; q < kQ; ++q)
-    for (int64_t n = 0; n < N; ++n) buf[q * h->pstride + n] = (float)dev[q * N + n];
+  for_each_population(h, [&](int64_t hi, int64_t di) { buf[di] = (float)dev[hi]; });
   return h->hip(hipMemcpy(h->pop[cur], buf.data(), buf.size() * 4, hipMemcpyHostToDevice), "hipMemcpy");
 }
 
@@ -958,20 +1085,19 @@ int lbm_get_populations(lbm_handle* h, double* dev) {
   int rc = h->hip(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
   if (rc) return rc;
   const int cur = (int)(h->host_step & 1);
-  const int64_t N = h->nodes;
   if (h->storage == LBM_FP16_SHIFTED) {
     std::vector<_Float16> buf(kQ * (size_t)h->pstride);
     rc = h->hip(hipMemcpy(buf.data(), h->pop[cur], buf.size() * 2, hipMemcpyDeviceToHost), "hipMemcpy");
     if (rc) return rc;
-    for (int q = 0; q < kQ; ++q)
-      for (int64_t n = 0; n < N; ++n) dev[q * N + n] = (double)((float)buf[q * h->pstride + n] / h->fp16_scale);
+    for_each_population(h, [&](int64_t hi, int64_t di) {
+      dev[hi] = (double)((float)buf[di] / h->fp16_scale);
+    });
     return LBM_OK;
   }
   std::vector<float> buf(kQ * (size_t)h->pstride);
   rc = h->hip(hipMemcpy(buf.data(), h->pop[cur], buf.size() * 4, hipMemcpyDeviceToHost), "hipMemcpy");
   if (rc) return rc;
-  for (int q = 0; q < kQ; ++q)
-    for (int64_t n = 0; n < N; ++n) dev[q * N + n] = (double)buf[q * h->pstride + n];
+  for_each_population(h, [&](int64_t hi, int64_t di) { dev[hi] = (double)buf[di]; });
   return LBM_OK;
 }
 
@@ -979,9 +1105,9 @@ int lbm_get_populations(lbm_handle* h, double* dev) {
 namespace {
 struct CkptHeader {
   uint32_t magic, version;
-  int32_t nx, ny, nz, storage, width, forcing, nm, nbeads;
-  double tau;
-  int64_t step;
+  int32_t nboxes, storage, width, nm, nbeads, pad;
+  uint64_t signature;
+  int64_t nodes, step;
 };
 
 int io_blob(lbm_handle* h, FILE* f, void* dptr, size_t bytes, bool save) {
@@ -1004,16 +1130,16 @@ int checkpoint(lbm_handle* h, const char* path, bool save) {
   if (rc) return rc;
   FILE* f = fopen(path, save ? "wb" : "rb");
   if (!f) return h->fail(LBM_EIO, std::string("cannot open ") + path);
-  CkptHeader hd{kMagic, 1, h->grid.nx, h->grid.ny, h->grid.nz, h->storage, h->width, h->forcing,
-                h->nm, (int32_t)h->beads.size(), h->tau, h->host_step};
+  CkptHeader hd{kMagic, 2, (int32_t)h->boxes.size(), h->storage, h->width, h->nm, (int32_t)h->beads.size(),
+                0, signature(h), h->nodes, h->host_step};
   if (save) {
     if (fwrite(&hd, sizeof hd, 1, f) != 1) rc = h->fail(LBM_EIO, "short write");
   } else {
     CkptHeader in{};
     if (fread(&in, sizeof in, 1, f) != 1) rc = h->fail(LBM_EIO, "short read");
-    else if (in.magic != kMagic || in.version != 1 || in.nx != hd.nx || in.ny != hd.ny || in.nz != hd.nz ||
-             in.storage != hd.storage || in.width != hd.width || in.forcing != hd.forcing ||
-             in.nm != hd.nm || in.nbeads != hd.nbeads || in.tau != hd.tau)
+    else if (in.magic != kMagic || in.version != hd.version || in.nboxes != hd.nboxes ||
+             in.storage != hd.storage || in.width != hd.width || in.nm != hd.nm || in.nbeads != hd.nbeads ||
+             in.signature != hd.signature || in.nodes != hd.nodes)
       rc = h->fail(LBM_EINVAL, "checkpoint does not match this handle");
     else
       h->host_step = in.step;
@@ -1095,19 +1221,162 @@ int lbm_probe_copy_bandwidth(int64_t bytes, int iters, double* gbs) {
 
 int lbm_set_stream_collide_launch(lbm_handle* h, int block, int xcd_remap, int resident) {
   if (!h || (block != 128 && block != 256 && block != 512) || resident < -1 || resident > 64) return LBM_EINVAL;
-  if (h->boxes.size() != 1) return h->fail(LBM_ESTATE, "launch shape of a batch is set by its tuner");
   int rc = h->hip(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
   if (rc) return rc;
   h->sc_block = block;
   h->sc_remap = xcd_remap ? 1 : 0;
   h->sc_resident = resident;
-  h->sc_blocks = (int)((h->nodes + block - 1) / block);
+  rc = build_sc_tables(h);
+  if (rc) return rc;
   set_near_bounds(h);
   h->need_prologue = true;
   if (h->g_chunk) (void)hipGraphExecDestroy(h->g_chunk);
   if (h->g_one) (void)hipGraphExecDestroy(h->g_one);
   h->g_chunk = h->g_one = nullptr;
   return LBM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Device copy of every buffer that stepping changes, for the tuner.
+struct Snapshot {
+  std::vector<std::pair<void*, size_t>> parts;
+  char* mem = nullptr;
+  int64_t host_step = 0;
+};
+
+void snapshot_parts(lbm_handle* h, Snapshot& S) {
+  const size_t pb = (size_t)element_bytes(h) * kQ * h->pstride;
+  S.parts = {{h->pop[0], pb}, {h->pop[1], pb}, {h->F, sizeof(float) * 3 * h->pstride},
+             {h->u, sizeof(float) * 3 * h->pstride}, {h->stamp, sizeof(int) * h->ntiles},
+             {h->d_step, sizeof(int64_t)}, {h->d_overflow, sizeof(int)}};
+  if (h->uploaded && h->nm > 0) {
+    const size_t nsc_max = (size_t)((h->nodes + 127) / 128);
+    S.parts.push_back({h->d_pos, sizeof(double) * 3 * h->nm});
+    S.parts.push_back({h->d_U, sizeof(float) * 3 * h->nm});
+    S.parts.push_back({h->d_fm, sizeof(float) * 3 * h->nm});
+    S.parts.push_back({h->d_bstate, sizeof(BeadState) * h->beads.size()});
+    S.parts.push_back({h->d_near, sizeof(int) * 2 * nsc_max});
+    S.parts.push_back({h->d_near_list, sizeof(int) * 2 * nsc_max});
+    S.parts.push_back({h->d_near_count, sizeof(int) * 2});
+  }
+}
+
+int snapshot_copy(lbm_handle* h, Snapshot& S, bool take) {
+  size_t off = 0;
+  for (auto& p : S.parts) {
+    void* dst = take ? (void*)(S.mem + off) : p.first;
+    const void* src = take ? p.first : (const void*)(S.mem + off);
+    int rc = h->hip(hipMemcpyAsync(dst, src, p.second, hipMemcpyDeviceToDevice, h->stream), "hipMemcpyAsync");
+    if (rc) return rc;
+    off += (p.second + 255) / 256 * 256;
+  }
+  if (take)
+    S.host_step = h->host_step;
+  else
+    h->host_step = S.host_step;
+  h->need_prologue = true;
+  return h->hip(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+}
+
+std::string tune_key(const lbm_handle* h) {
+  char buf[128];
+  std::snprintf(buf, sizeof buf, "lbmib-tune-v1 %016llx cu%d", (unsigned long long)signature(h), h->ncu);
+  return buf;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_autotune(lbm_handle* h, int32_t steps, const char* cache_path, char* report, int32_t report_len) {
+  if (!h || steps < 1) return LBM_EINVAL;
+  int rc = upload(h);
+  if (rc) return rc;
+  std::string rep;
+  const std::string key = tune_key(h);
+  if (cache_path) {
+    if (FILE* f = fopen(cache_path, "r")) {
+      char line[256];
+      int blk = 0, remap = 0, res = 0;
+      bool hit = false;
+      while (fgets(line, sizeof line, f)) {
+        char k1[64], k2[64], k3[64];
+        double us;
+        if (sscanf(line, "%63s %63s %63s %d %d %d %lf", k1, k2, k3, &blk, &remap, &res, &us) == 7 &&
+            key == std::string(k1) + " " + k2 + " " + k3)
+          hit = true;
+        if (hit) break;
+      }
+      fclose(f);
+      if (hit) {
+        rc = lbm_set_stream_collide_launch(h, blk, remap, res);
+        if (!rc && report && report_len > 0) std::snprintf(report, report_len, "cached %d %d %d\n", blk, remap, res);
+        return rc;
+      }
+    }
+  }
+  struct Cand {
+    int block, remap, resident;
+  };
+  std::vector<Cand> cands;
+  const std::vector<int> residents = h->swimmers.empty() ? std::vector<int>{0} : std::vector<int>{-1, 0, 2};
+  for (int blk : {128, 256, 512})
+    for (int remap : {0, 1})
+      for (int res : residents) cands.push_back({blk, remap, res});
+  Snapshot S;
+  snapshot_parts(h, S);
+  size_t total = 0;
+  for (auto& p : S.parts) total += (p.second + 255) / 256 * 256;
+  if (hipMalloc(&S.mem, total) != hipSuccess) return h->fail(LBM_ENOMEM, "tuner snapshot allocation failed");
+  rc = snapshot_copy(h, S, true);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (!rc) rc = h->hip(hipEventCreate(&e0), "hipEventCreate");
+  if (!rc) rc = h->hip(hipEventCreate(&e1), "hipEventCreate");
+  const int old_block = h->sc_block, old_remap = h->sc_remap, old_res = h->sc_resident;
+  double best = 1e300;
+  Cand win{old_block, old_remap, old_res};
+  const bool old_graphs = h->use_graphs;
+  h->use_graphs = true;
+  for (const Cand& c : cands) {
+    if (rc) break;
+    rc = lbm_set_stream_collide_launch(h, c.block, c.remap, c.resident);
+    if (!rc) rc = snapshot_copy(h, S, false);
+    if (!rc) rc = lbm_step(h, 2 * kGraphChunk);
+    if (!rc) rc = h->hip(hipEventRecord(e0, h->stream), "hipEventRecord");
+    if (!rc) rc = lbm_step(h, steps);
+    if (!rc) rc = h->hip(hipEventRecord(e1, h->stream), "hipEventRecord");
+    if (!rc) rc = h->hip(hipEventSynchronize(e1), "hipEventSynchronize");
+    if (!rc) rc = check_overflow(h);
+    float ms = 0;
+    if (!rc) rc = h->hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+    if (rc) break;
+    const double us = 1e3 * ms / steps;
+    char line[96];
+    std::snprintf(line, sizeof line, "%d %d %d %.3f\n", c.block, c.remap, c.resident, us);
+    rep += line;
+    if (us < best) {
+      best = us;
+      win = c;
+    }
+  }
+  h->use_graphs = old_graphs;
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  int rc2 = lbm_set_stream_collide_launch(h, win.block, win.remap, win.resident);
+  if (!rc2) rc2 = snapshot_copy(h, S, false);
+  (void)hipFree(S.mem);
+  if (!rc) rc = rc2;
+  if (!rc && cache_path && best < 1e300) {
+    FILE* f = fopen(cache_path, "a");
+    if (!f) return h->fail(LBM_EIO, std::string("cannot append to ") + cache_path);
+    fprintf(f, "%s %d %d %d %.3f\n", key.c_str(), win.block, win.remap, win.resident, best);
+    fclose(f);
+  }
+  if (report && report_len > 0) std::snprintf(report, report_len, "%s", rep.c_str());
+  return rc;
 }
 
 int64_t lbm_bytes_per_step(const lbm_handle* h) {

@@ -28,6 +28,8 @@ SYMBOLS = [
     "lbm_get_density", "lbm_get_conserved", "lbm_set_populations", "lbm_get_populations",
     "lbm_save", "lbm_load", "lbm_set_kernel_timing", "lbm_kernel_time", "lbm_bytes_per_step",
     "lbm_probe_copy_bandwidth", "lbm_set_stream_collide_launch",
+    "lbm_batch_create", "lbm_batch_swimmer_add", "lbm_n_boxes", "lbm_batch_get_velocity",
+    "lbm_batch_get_conserved", "lbm_autotune",
     "lbm_strerror", "lbm_last_error",
 ]
 
@@ -45,6 +47,10 @@ class Grid(C.Structure):
 class Opts(C.Structure):
     _fields_ = [("storage", C.c_int32), ("delta_width", C.c_int32), ("fp16_scale", C.c_float),
                 ("use_graphs", C.c_int32), ("stream", C.c_void_p)]
+
+
+class BoxDesc(C.Structure):
+    _fields_ = [("grid", Grid), ("tau", C.c_double), ("forcing", C.c_int32)]
 
 
 class BeadDesc(C.Structure):
@@ -111,6 +117,13 @@ def load_library():
         "lbm_bytes_per_step": (i64, [vp]),
         "lbm_probe_copy_bandwidth": (C.c_int, [i64, C.c_int, C.POINTER(C.c_double)]),
         "lbm_set_stream_collide_launch": (C.c_int, [vp, C.c_int, C.c_int, C.c_int]),
+        "lbm_batch_create": (C.c_int, [C.POINTER(BoxDesc), i32, C.POINTER(Opts), C.POINTER(C.c_void_p)]),
+        "lbm_batch_swimmer_add": (C.c_int, [vp, i32, C.POINTER(BeadDesc), C.POINTER(SpringDesc),
+                                            C.POINTER(ActuationDesc), C.POINTER(i32)]),
+        "lbm_n_boxes": (i32, [vp]),
+        "lbm_batch_get_velocity": (C.c_int, [vp, i32, fp, C.c_int]),
+        "lbm_batch_get_conserved": (C.c_int, [vp, i32, dp]),
+        "lbm_autotune": (C.c_int, [vp, i32, C.c_char_p, C.c_char_p, i32]),
         "lbm_strerror": (C.c_char_p, [C.c_int]),
         "lbm_last_error": (C.c_char_p, [vp]),
     }
@@ -137,6 +150,23 @@ def _hip_runtimes():
 
 def _ptr(a):
     return a.ctypes.data_as(C.c_void_p)
+
+
+def _swimmer_descs(sw):
+    beads = (BeadDesc * 3)()
+    for k in range(3):
+        beads[k].centre[:] = [float(v) for v in sw["centres"][k]]
+        beads[k].radius = float(sw["radius"][k])
+        beads[k].level = int(sw["level"])
+        beads[k].kappa_s = float(sw["ks"])
+        beads[k].C = float(sw["C"])
+        beads[k].kappa_b = float(sw["kb"])
+        beads[k].kappa_v = float(sw["kv"])
+    springs = (SpringDesc * 2)(SpringDesc(float(sw["k"][0]), float(sw["L0"][0])),
+                               SpringDesc(float(sw["k"][1]), float(sw["L0"][1])))
+    act = ActuationDesc(float(sw["A"]), float(sw["B"]), float(sw["T"]), float(sw["alpha"]),
+                        float(sw["phi0"]))
+    return beads, springs, act
 
 
 class Lattice:
@@ -186,19 +216,7 @@ class Lattice:
     # -- setup
     def add_swimmer(self, sw):
         """Add a swimmer described by a ``workloads.swimmer`` dict."""
-        beads = (BeadDesc * 3)()
-        for k in range(3):
-            beads[k].centre[:] = [float(v) for v in sw["centres"][k]]
-            beads[k].radius = float(sw["radius"][k])
-            beads[k].level = int(sw["level"])
-            beads[k].kappa_s = float(sw["ks"])
-            beads[k].C = float(sw["C"])
-            beads[k].kappa_b = float(sw["kb"])
-            beads[k].kappa_v = float(sw["kv"])
-        springs = (SpringDesc * 2)(SpringDesc(float(sw["k"][0]), float(sw["L0"][0])),
-                                   SpringDesc(float(sw["k"][1]), float(sw["L0"][1])))
-        act = ActuationDesc(float(sw["A"]), float(sw["B"]), float(sw["T"]), float(sw["alpha"]),
-                            float(sw["phi0"]))
+        beads, springs, act = _swimmer_descs(sw)
         sid = C.c_int32()
         self._check(self.lib.lbm_swimmer_add(self.h, beads, springs, C.byref(act), C.byref(sid)))
         return sid.value
@@ -306,6 +324,14 @@ class Lattice:
         self._check(self.lib.lbm_set_stream_collide_launch(self.h, int(block), int(bool(xcd_remap)),
                                                            int(resident)))
 
+    def autotune(self, steps_per_candidate=64, cache_path=None):
+        """Pick the fastest stream-collide launch shape (state is restored);
+        returns the per-candidate report lines."""
+        buf = C.create_string_buffer(4096)
+        cp = None if cache_path is None else str(cache_path).encode()
+        self._check(self.lib.lbm_autotune(self.h, int(steps_per_candidate), cp, buf, 4096))
+        return buf.value.decode()
+
     @property
     def bytes_per_step(self):
         return self.lib.lbm_bytes_per_step(self.h)
@@ -325,6 +351,75 @@ def copy_bandwidth(nbytes=1 << 30, iters=20):
     if rc:
         raise LbmError(rc, lib.lbm_strerror(rc).decode())
     return out.value
+
+
+class Batch(Lattice):
+    """Independent periodic boxes stepped together (one launch per kernel per
+    step over all boxes).  ``boxes``: list of (shape, tau, forcing)."""
+
+    def __init__(self, boxes, storage=FP32_SHIFTED, width=3, fp16_scale=1.0, use_graphs=True,
+                 stream=None):
+        self.lib = load_library()
+        self.shapes = [tuple(int(v) for v in b[0]) for b in boxes]
+        self.shape = self.shapes[0]
+        self.storage = storage
+        raw = None
+        if stream is not None:
+            raw = int(getattr(stream, "cuda_stream", stream)) or None
+        arr = (BoxDesc * len(boxes))()
+        for i, (shape, tau, forcing) in enumerate(boxes):
+            arr[i].grid = Grid(*[int(v) for v in shape])
+            arr[i].tau = float(tau)
+            arr[i].forcing = int(forcing)
+        o = Opts(int(storage), int(width), float(fp16_scale), int(bool(use_graphs)), raw)
+        h = C.c_void_p()
+        rc = self.lib.lbm_batch_create(arr, len(boxes), C.byref(o), C.byref(h))
+        if rc:
+            raise LbmError(rc, self.lib.lbm_strerror(rc).decode())
+        self.h = h
+
+    @property
+    def N(self):
+        return sum(nx * ny * nz for nx, ny, nz in self.shapes)
+
+    @property
+    def n_boxes(self):
+        return self.lib.lbm_n_boxes(self.h)
+
+    def add_swimmer(self, sw, box=0):
+        beads, springs, act = _swimmer_descs(sw)
+        sid = C.c_int32()
+        self._check(self.lib.lbm_batch_swimmer_add(self.h, int(box), beads, springs, C.byref(act),
+                                                   C.byref(sid)))
+        return sid.value
+
+    def velocity(self, box=0):
+        nx, ny, nz = self.shapes[box]
+        out = np.zeros((3, nz, ny, nx), np.float32)
+        self._check(self.lib.lbm_batch_get_velocity(self.h, int(box), _ptr(out), 0))
+        return out
+
+    def conserved(self, box=-1):
+        out = np.zeros(4)
+        self._check(self.lib.lbm_batch_get_conserved(self.h, int(box), _ptr(out)))
+        return out
+
+    def populations(self):
+        out = np.zeros(19 * self.N)
+        self._check(self.lib.lbm_get_populations(self.h, _ptr(out)))
+        return out
+
+
+def batch_from_ensemble(ens, storage=FP32_SHIFTED, use_graphs=True, stream=None):
+    """Build a Batch from a ``workloads.ensemble`` dict (boxes share the
+    kernel width of the first box)."""
+    boxes = ens["boxes"]
+    b = Batch([(bx["shape"], bx["tau"], bx["forcing"]) for bx in boxes], storage,
+              boxes[0]["width"], use_graphs=use_graphs, stream=stream)
+    for i, bx in enumerate(boxes):
+        for sw in bx["swimmers"]:
+            b.add_swimmer(sw, box=i)
+    return b
 
 
 def from_workload(case, storage=FP32_SHIFTED, fp16_scale=1.0, use_graphs=True, stream=None):

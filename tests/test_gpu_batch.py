@@ -1,0 +1,83 @@
+"""GPU parity of the batched form: many independent periodic boxes of uneven
+size, each with its own tau and swimmer, advanced together (one launch per
+kernel per step, graph-replayed), against the FP64 oracle run box by box.
+
+Tolerances as for the single box (tests/test_gpu_swimmer.py): velocity
+rel-L2 <= 1e-5, marker positions within 1e-10 lattice units per step."""
+import numpy as np
+import pytest
+
+from paper_2202_12147_amd import lbmib, workloads as wl
+from tests.helpers import oracle_from, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+POS_PER_STEP = 1e-10
+
+
+def _box_case(bx):
+    return dict(shape=bx["shape"], tau=bx["tau"], forcing=bx["forcing"], width=bx["width"],
+                swimmers=bx["swimmers"])
+
+
+def test_batch_of_one_equals_single_handle():
+    case = wl.small_case()
+    a = lbmib.from_workload(case)
+    b = lbmib.Batch([(case["shape"], case["tau"], case["forcing"])], width=case["width"])
+    b.add_swimmer(case["swimmers"][0], box=0)
+    for x in (a, b):
+        x.step(70)
+    assert np.array_equal(a.markers(), b.markers())
+    assert np.array_equal(a.velocity(), b.velocity(0))
+    assert np.array_equal(a.populations().ravel(), b.populations())
+
+
+def test_boxes_do_not_interact():
+    ens = wl.ensemble(seed=3, nboxes=3)
+    full = lbmib.batch_from_ensemble(ens)
+    alone = lbmib.batch_from_ensemble(dict(ens, boxes=ens["boxes"][1:2]))
+    full.step(50)
+    alone.step(50)
+    nv = full.n_markers // 3
+    assert np.array_equal(full.velocity(1), alone.velocity(0))
+    assert np.array_equal(full.markers()[nv:2 * nv], alone.markers())
+
+
+def test_ensemble_parity_sampled_boxes():
+    # the 64-box ensemble at full size, as the benchmark runs it; four boxes
+    # drawn by seed are compared with the oracle
+    ens = wl.ensemble(seed=0)
+    batch = lbmib.batch_from_ensemble(ens)
+    steps = 200
+    batch.step(steps)
+    batch.sync()
+    rng = np.random.default_rng(0)
+    picks = sorted(rng.choice(len(ens["boxes"]), 4, replace=False))
+    markers = batch.markers()
+    offsets = np.cumsum([0] + [3 * 162 for _ in ens["boxes"]])
+    for b in picks:
+        case = _box_case(ens["boxes"][b])
+        print("box", b, case["shape"], case["tau"], flush=True)
+        o = oracle_from(case)
+        o.step(steps)
+        assert rel_l2(batch.velocity(b), o.velocity()) < 1e-5
+        assert np.abs(markers[offsets[b]:offsets[b + 1]] - o.markers()).max() < POS_PER_STEP * steps
+        c = batch.conserved(b)
+        assert abs(c[0] - np.prod(case["shape"])) < 1e-6 and np.abs(c[1:]).max() < 1e-6
+
+
+def test_autotune_restores_state_and_caches(tmp_path):
+    ens = wl.ensemble(seed=5, nboxes=4)
+    a = lbmib.batch_from_ensemble(ens)
+    b = lbmib.batch_from_ensemble(ens)
+    a.step(40)
+    b.step(40)
+    cache = tmp_path / "tune.txt"
+    rep = a.autotune(16, cache)
+    assert len(rep.strip().splitlines()) == 18
+    a.step(25)
+    b.step(25)
+    assert np.array_equal(a.markers(), b.markers())
+    assert np.array_equal(a.populations(), b.populations())
+    assert a.time == b.time == 65
+    assert a.autotune(16, cache).startswith("cached")
