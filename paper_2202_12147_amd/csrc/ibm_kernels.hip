@@ -36,8 +36,16 @@ namespace lbmib {
 
 namespace {
 
-constexpr int kStatsBlock = 1024;
-constexpr int kSpreadBlock = kTile * kTile * kTile;  // 512, one thread per node
+// Workgroup sizes of the bead-statistics and spreading kernels: wide when a
+// handle has few beads (latency of a few workgroups dominates), small when it
+// has many (they run beside the bulk stream-collide launch and must fit into
+// the wave slots its retiring workgroups free).
+constexpr int kStatsBlock = 256;
+constexpr int kStatsBlockWide = 1024;
+constexpr int kTileNodes = kTile * kTile * kTile;  // 512
+constexpr int kSpreadBlock = 256;
+constexpr int kSpreadBlockWide = 512;
+constexpr int kWideBeads = 32;  // at most this many beads: wide workgroups
 constexpr int kInterpBlock = 256;
 
 __device__ inline int floor_div(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
@@ -126,9 +134,9 @@ __device__ inline void mark_near_blocks(const Dev& d, const Box& B, int box, con
   }
 }
 
-template <int NW>
-__global__ __launch_bounds__(kStatsBlock) void k_bead_stats(Dev d, int mark_offset) {
-  constexpr int NWAVE = kStatsBlock / 64;
+template <int NW, int BS>
+__global__ __launch_bounds__(BS) void k_bead_stats(Dev d, int mark_offset) {
+  constexpr int NWAVE = BS / 64;
   constexpr int NV = 10;  // sums x y z, min x y z, max x y z, volume
   __shared__ double part[NWAVE][NV];
   __shared__ int reg_lo[3], reg_hi[3];
@@ -140,7 +148,7 @@ __global__ __launch_bounds__(kStatsBlock) void k_bead_stats(Dev d, int mark_offs
   // centre keeps the products small, and lets one pass reduce everything.
   const double cx = d.bstate[b].c[0], cy = d.bstate[b].c[1], cz = d.bstate[b].c[2];
   double v[NV] = {0, 0, 0, 1e300, 1e300, 1e300, -1e300, -1e300, -1e300, 0};
-  for (int i = threadIdx.x; i < Bd.nv; i += kStatsBlock) {
+  for (int i = threadIdx.x; i < Bd.nv; i += BS) {
     const double3 p = load_pos(d.pos, d.nm, Bd.first + i);
     v[0] += p.x;
     v[1] += p.y;
@@ -152,7 +160,7 @@ __global__ __launch_bounds__(kStatsBlock) void k_bead_stats(Dev d, int mark_offs
     v[7] = fmax(v[7], p.y);
     v[8] = fmax(v[8], p.z);
   }
-  for (int t = threadIdx.x; t < Bd.ntri; t += kStatsBlock) {
+  for (int t = threadIdx.x; t < Bd.ntri; t += BS) {
     const int tt = Bd.tri0 + t;
     const double3 p0 = load_pos(d.pos, d.nm, d.tri[tt]);
     const double3 p1 = load_pos(d.pos, d.nm, d.tri[d.ntri + tt]);
@@ -412,11 +420,11 @@ __device__ inline bool stencil_offset(int base, int origin, int extent, int N, i
 // One workgroup per tile.  The markers whose stencils meet the tile are
 // compacted in (bead, marker) order; the thread that finds a marker stages its
 // stencil offset, its per-axis kernel weights and its force in LDS.  Entry e
-// goes to wavefront e % 8, which adds the marker's stencil (one lane per
-// stencil node, all distinct) into the wavefront's private LDS copy of the
-// tile; the eight copies are summed in wavefront order.  No atomics, fixed
+// goes to wavefront e % W (W wavefronts per workgroup), which adds the
+// marker's stencil (one lane per stencil node, all distinct) into the
+// wavefront's private LDS copy of the tile; the W copies are summed in
+// wavefront order.  No atomics, fixed
 // summation order: deterministic.
-constexpr int kSpreadWaves = kSpreadBlock / 64;
 template <int NW>
 struct SpreadEntry {
   int off;           // packed stencil offset from the tile origin, +8 per axis
@@ -424,10 +432,11 @@ struct SpreadEntry {
   float f[3];        // marker force
 };
 
-template <int NW>
-__global__ __launch_bounds__(kSpreadBlock) void k_spread(Dev d) {
-  __shared__ float acc[kSpreadWaves][3][kSpreadBlock];
-  __shared__ SpreadEntry<NW> ent[kSpreadBlock];
+template <int NW, int BS>
+__global__ __launch_bounds__(BS) void k_spread(Dev d) {
+  constexpr int kSpreadWaves = BS / 64;
+  __shared__ float acc[kSpreadWaves][3][kTileNodes];
+  __shared__ SpreadEntry<NW> ent[BS];
   __shared__ int wave_cnt[kSpreadWaves];
   const int blk = blockIdx.x;
   const int b = d.spread_bead[blk];
@@ -444,17 +453,18 @@ __global__ __launch_bounds__(kSpreadBlock) void k_spread(Dev d) {
   const int ox = tx * kTile, oy = ty * kTile, oz = tz * kTile;
   const int ex = min(kTile, B.nx - ox), ey = min(kTile, B.ny - oy), ez = min(kTile, B.nz - oz);
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
-  for (int w = 0; w < kSpreadWaves; ++w) {
-    acc[w][0][threadIdx.x] = 0.0f;
-    acc[w][1][threadIdx.x] = 0.0f;
-    acc[w][2][threadIdx.x] = 0.0f;
-  }
+  for (int w = 0; w < kSpreadWaves; ++w)
+    for (int nd = threadIdx.x; nd < kTileNodes; nd += BS) {
+      acc[w][0][nd] = 0.0f;
+      acc[w][1][nd] = 0.0f;
+      acc[w][2][nd] = 0.0f;
+    }
   // stencil node of this lane (NW^3 <= 64 lanes used)
   const int sa = lane % NW, sb = (lane / NW) % NW, sc = lane / (NW * NW);
   for (int b2 = b; b2 < B.bead0 + B.nbeads; ++b2) {
     if (b2 != b && !covers(d.bstate[b2], tx, ty, tz, B)) continue;
     const Bead Q = d.beads[b2];
-    for (int c0 = 0; c0 < Q.nv; c0 += kSpreadBlock) {
+    for (int c0 = 0; c0 < Q.nv; c0 += BS) {
       const int i = c0 + (int)threadIdx.x;
       bool take = false;
       int offx = 0, offy = 0, offz = 0;
@@ -515,18 +525,20 @@ __global__ __launch_bounds__(kSpreadBlock) void k_spread(Dev d) {
     }
   }
   __syncthreads();
-  const int lx = threadIdx.x % kTile, ly = (threadIdx.x / kTile) % kTile, lz = threadIdx.x / (kTile * kTile);
-  if (lx < ex && ly < ey && lz < ez) {
-    float ax = 0, ay = 0, az = 0;
-    for (int w = 0; w < kSpreadWaves; ++w) {
-      ax += acc[w][0][threadIdx.x];
-      ay += acc[w][1][threadIdx.x];
-      az += acc[w][2][threadIdx.x];
+  for (int nd = threadIdx.x; nd < kTileNodes; nd += BS) {
+    const int lx = nd % kTile, ly = (nd / kTile) % kTile, lz = nd / (kTile * kTile);
+    if (lx < ex && ly < ey && lz < ez) {
+      float ax = 0, ay = 0, az = 0;
+      for (int w = 0; w < kSpreadWaves; ++w) {
+        ax += acc[w][0][nd];
+        ay += acc[w][1][nd];
+        az += acc[w][2][nd];
+      }
+      const int64_t node = B.node0 + (int64_t)(oz + lz) * B.nx * B.ny + (int64_t)(oy + ly) * B.nx + (ox + lx);
+      d.F[node] = ax;
+      d.F[d.pstride + node] = ay;
+      d.F[2 * d.pstride + node] = az;
     }
-    const int64_t node = B.node0 + (int64_t)(oz + lz) * B.nx * B.ny + (int64_t)(oy + ly) * B.nx + (ox + lx);
-    d.F[node] = ax;
-    d.F[d.pstride + node] = ay;
-    d.F[2 * d.pstride + node] = az;
   }
   if (threadIdx.x == 0) d.stamp[B.tile0 + tx + B.tx * (ty + B.ty * tz)] = (int)n;
 }
@@ -589,10 +601,18 @@ __global__ __launch_bounds__(kStatsBlock) void k_bead_centres(Dev d, double* out
 
 }  // namespace
 
+template <int BS>
+static void launch_stats_bs(const Dev& d, int mark_offset, hipStream_t s) {
+  if (d.width == 2) hipLaunchKernelGGL((k_bead_stats<2, BS>), dim3(d.nbeads), dim3(BS), 0, s, d, mark_offset);
+  else if (d.width == 3) hipLaunchKernelGGL((k_bead_stats<3, BS>), dim3(d.nbeads), dim3(BS), 0, s, d, mark_offset);
+  else hipLaunchKernelGGL((k_bead_stats<4, BS>), dim3(d.nbeads), dim3(BS), 0, s, d, mark_offset);
+}
+
 void launch_bead_stats(const Dev& d, int mark_offset, hipStream_t s) {
-  if (d.width == 2) hipLaunchKernelGGL(k_bead_stats<2>, dim3(d.nbeads), dim3(kStatsBlock), 0, s, d, mark_offset);
-  else if (d.width == 3) hipLaunchKernelGGL(k_bead_stats<3>, dim3(d.nbeads), dim3(kStatsBlock), 0, s, d, mark_offset);
-  else hipLaunchKernelGGL(k_bead_stats<4>, dim3(d.nbeads), dim3(kStatsBlock), 0, s, d, mark_offset);
+  if (d.nbeads <= kWideBeads)
+    launch_stats_bs<kStatsBlockWide>(d, mark_offset, s);
+  else
+    launch_stats_bs<kStatsBlock>(d, mark_offset, s);
 }
 
 void launch_vertex_forces(const Dev& d, hipStream_t s) {
@@ -600,10 +620,18 @@ void launch_vertex_forces(const Dev& d, hipStream_t s) {
   hipLaunchKernelGGL(k_vertex_forces, dim3(blocks), dim3(256), 0, s, d);
 }
 
+template <int BS>
+static void launch_spread_bs(const Dev& d, hipStream_t s) {
+  if (d.width == 2) hipLaunchKernelGGL((k_spread<2, BS>), dim3(d.spread_blocks), dim3(BS), 0, s, d);
+  else if (d.width == 3) hipLaunchKernelGGL((k_spread<3, BS>), dim3(d.spread_blocks), dim3(BS), 0, s, d);
+  else hipLaunchKernelGGL((k_spread<4, BS>), dim3(d.spread_blocks), dim3(BS), 0, s, d);
+}
+
 void launch_spread(const Dev& d, hipStream_t s) {
-  if (d.width == 2) hipLaunchKernelGGL(k_spread<2>, dim3(d.spread_blocks), dim3(kSpreadBlock), 0, s, d);
-  else if (d.width == 3) hipLaunchKernelGGL(k_spread<3>, dim3(d.spread_blocks), dim3(kSpreadBlock), 0, s, d);
-  else hipLaunchKernelGGL(k_spread<4>, dim3(d.spread_blocks), dim3(kSpreadBlock), 0, s, d);
+  if (d.nbeads <= kWideBeads)
+    launch_spread_bs<kSpreadBlockWide>(d, s);
+  else
+    launch_spread_bs<kSpreadBlock>(d, s);
 }
 
 void launch_interp_advance(const Dev& d, hipStream_t s) {

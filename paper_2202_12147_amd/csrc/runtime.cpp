@@ -1322,7 +1322,7 @@ int lbm_autotune(lbm_handle* h, int32_t steps, const char* cache_path, char* rep
     int block, remap, resident;
   };
   std::vector<Cand> cands;
-  const std::vector<int> residents = h->swimmers.empty() ? std::vector<int>{0} : std::vector<int>{-1, 0, 2};
+  const std::vector<int> residents = h->swimmers.empty() ? std::vector<int>{0} : std::vector<int>{-1, 0, 2, 6};
   for (int blk : {128, 256, 512})
     for (int remap : {0, 1})
       for (int res : residents) cands.push_back({blk, remap, res});

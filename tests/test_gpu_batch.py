@@ -74,7 +74,7 @@ def test_autotune_restores_state_and_caches(tmp_path):
     b.step(40)
     cache = tmp_path / "tune.txt"
     rep = a.autotune(16, cache)
-    assert len(rep.strip().splitlines()) == 18
+    assert len(rep.strip().splitlines()) == 24
     a.step(25)
     b.step(25)
     assert np.array_equal(a.markers(), b.markers())
