@@ -111,7 +111,7 @@ def adjoint_case(reduced=False):
     mid = tuple(s // 2 for s in shape)
     return dict(name=f"adjoint {shape[0]}^3", shape=shape, tau=1.0, forcing=GUO, width=3,
                 steps=2000, checkpoint=100,
-                swimmers=[swimmer(mid, sp, A=1e-3, T=2000.0, alpha=math.pi / 2)])
+                swimmers=[swimmer(mid, sp, A=1e-3, T=2000.0, alpha=math.pi / 3)])
 
 
 def random_deviation(shape, seed=0, eps=1e-4, modes=3):
