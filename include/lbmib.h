@@ -217,6 +217,39 @@ int lbm_batch_get_conserved(lbm_handle* h, int32_t box, double out[4]);
 int lbm_autotune(lbm_handle* h, int32_t steps_per_candidate, const char* cache_path, char* report,
                  int32_t report_len);
 
+/* ---- gradient of the swimming displacement (discrete adjoint) -------------- */
+/* Set the four parameters the adjoint differentiates of swimmer `swimmer`:
+ * driving amplitudes A (bead 1) and B (bead 3), their phase shift alpha
+ * (Sec. 2.2) and the constant k of both springs.  Allowed at any time; the
+ * next step uses them.  Errors: LBM_EINVAL (no such swimmer), LBM_EDEVICE. */
+int lbm_swimmer_set_params(lbm_handle* h, int32_t swimmer, double A, double B, double alpha, double k);
+
+typedef struct {
+  int64_t steps;      /* T: steps of the forward run (>= 1) */
+  int32_t checkpoint; /* K: forward state kept every K steps, the reverse
+                         sweep recomputes each K-step segment (>= 1; K >= T
+                         stores the whole run) */
+  int32_t swimmer;    /* objective swimmer */
+  int32_t rewind;     /* nonzero: restore the state held at entry on return */
+} lbm_adjoint_desc;
+
+/* Objective J = x_cm(t0 + T) - x_cm(t0), the x displacement of swimmer
+ * `swimmer`'s centre (mean of its three bead centres, Eq. vel_swim) over T
+ * steps from the current state t0, and its exact gradient through the
+ * discrete time stepping (the transposed linearisation of every operation of
+ * lbm_step: collision, streaming, spreading, interpolation, advection and the
+ * membrane, spring and driving forces of Sec. 2.2) with respect to
+ * (A, B, alpha, k) of that swimmer: host grad[0..3] = dJ/dA, dJ/dB,
+ * dJ/dalpha, dJ/dk (k scales both springs).  The forward run is ordinary
+ * stepping, so on return the handle has advanced T steps exactly as lbm_step
+ * would have taken it (unless `rewind`).  Device memory: 19*4 bytes per node
+ * per checkpoint, 16 bytes per node per segment step, plus four population
+ * sets.  The adjoint arithmetic is FP32 on the grid and FP64 on the markers
+ * and parameter sums.  Single-box handles with FP32 storage and Guo forcing
+ * only.  Errors: LBM_EINVAL (bad descriptor, batch, FP16 storage, Shan-Chen
+ * forcing), LBM_ENOMEM, LBM_EDEVICE, LBM_EOVERFLOW. */
+int lbm_adjoint(lbm_handle* h, const lbm_adjoint_desc* desc, double* J, double grad[4]);
+
 /* ---- checkpoint ---------------------------------------------------------------- */
 /* Write / restore the full dynamic state (populations, forces, tile stamps,
  * markers, step counter) to / from a file.  Restoring needs a handle created

@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbmib.so")
-SOURCES = ["lattice_kernels.hip", "ibm_kernels.hip", "runtime.cpp"]
+SOURCES = ["lattice_kernels.hip", "ibm_kernels.hip", "adjoint_kernels.hip", "runtime.cpp", "adjoint.cpp"]
 ARCH = os.environ.get("LBMIB_ARCH", "gfx950")
 
 FLAGS = [

@@ -1,0 +1,287 @@
+// Host side of the discrete adjoint: checkpointed forward run, segment
+// recompute recording (rho, u) per step, and the reverse sweep.
+//
+// The forward run is plain stepping (lbm_step) with the populations, markers
+// and bead statistics copied aside every K steps.  Segments are then taken in
+// reverse order: the segment's forward steps are recomputed from its
+// checkpoint on scratch buffers (the serial kernel order of lbm_step, so the
+// trajectory is bitwise the forward one), keeping per step the markers, the
+// bead statistics, the marker forces and (rho, u) of every node; then its
+// reverse steps run from last to first.  The handle's own state is only
+// touched by the forward run.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "adjoint.h"
+#include "handle.h"
+
+using namespace lbmib;
+
+namespace lbmib {
+namespace rt {
+
+// Reverse-sweep buffers, kept on the handle between calls.
+struct AdjWork {
+  int64_t nck = 0;
+  int K = 0;
+  std::vector<void*> allocs;
+  float* ck_pop = nullptr;      // [nck][19][pstride]
+  double* ck_pos = nullptr;     // [nck][3][nm]
+  BeadState* ck_bst = nullptr;  // [nck][nbeads]
+  float* P = nullptr;           // [2][19][pstride] recompute populations
+  float* L = nullptr;           // [2][19][pstride] adjoint populations
+  float4* mom = nullptr;        // [K][nodes]
+  double* pslab = nullptr;      // [K+1][3][nm]
+  BeadState* bslab = nullptr;   // [K+1][nbeads]
+  float* fslab = nullptr;       // [K][3][nm]
+  float *F = nullptr, *u = nullptr, *lu = nullptr, *lF = nullptr;  // [3][pstride]
+  float* U = nullptr;           // [3][nm]
+  int* stamp = nullptr;
+  int64_t* step = nullptr;
+  int *near = nullptr, *near_list = nullptr, *near_count = nullptr, *overflow = nullptr;
+  double *lr = nullptr, *lfm = nullptr, *ltmp = nullptr, *bsum = nullptr, *grad = nullptr;
+  float* lr32 = nullptr;
+
+  ~AdjWork() {
+    for (void* p : allocs) (void)hipFree(p);
+  }
+  template <class T>
+  T* alloc(size_t n, int& rc) {
+    if (rc) return nullptr;
+    T* p = dev_alloc<T>(n, rc);
+    if (p) allocs.push_back(p);
+    return p;
+  }
+};
+
+void adjoint_release(lbm_handle* h) {
+  delete h->adj;
+  h->adj = nullptr;
+}
+
+namespace {
+
+int ensure_work(lbm_handle* h, int64_t nck, int K) {
+  if (h->adj && h->adj->nck >= nck && h->adj->K == K) return LBM_OK;
+  adjoint_release(h);
+  auto* w = new AdjWork;
+  int rc = LBM_OK;
+  const size_t ps = (size_t)h->pstride, nm = (size_t)h->nm, nb = h->beads.size();
+  const size_t nsc_max = (size_t)((h->nodes + 127) / 128);
+  w->nck = nck;
+  w->K = K;
+  w->ck_pop = w->alloc<float>((size_t)nck * kQ * ps, rc);
+  w->ck_pos = w->alloc<double>((size_t)nck * 3 * nm, rc);
+  w->ck_bst = w->alloc<BeadState>((size_t)nck * nb, rc);
+  w->P = w->alloc<float>(2 * kQ * ps, rc);
+  w->L = w->alloc<float>(2 * kQ * ps, rc);
+  w->mom = w->alloc<float4>((size_t)K * h->nodes, rc);
+  w->pslab = w->alloc<double>((size_t)(K + 1) * 3 * nm, rc);
+  w->bslab = w->alloc<BeadState>((size_t)(K + 1) * nb, rc);
+  w->fslab = w->alloc<float>((size_t)K * 3 * nm, rc);
+  w->F = w->alloc<float>(3 * ps, rc);
+  w->u = w->alloc<float>(3 * ps, rc);
+  w->lu = w->alloc<float>(3 * ps, rc);
+  w->lF = w->alloc<float>(3 * ps, rc);
+  w->U = w->alloc<float>(3 * nm, rc);
+  w->stamp = w->alloc<int>((size_t)h->ntiles, rc);
+  w->step = w->alloc<int64_t>(1, rc);
+  w->near = w->alloc<int>(2 * nsc_max, rc);
+  w->near_list = w->alloc<int>(2 * nsc_max, rc);
+  w->near_count = w->alloc<int>(2, rc);
+  w->overflow = w->alloc<int>(1, rc);
+  w->lr = w->alloc<double>(3 * nm, rc);
+  w->lfm = w->alloc<double>(3 * nm, rc);
+  w->ltmp = w->alloc<double>(3 * nm, rc);
+  w->bsum = w->alloc<double>(4 * nb, rc);
+  w->grad = w->alloc<double>(4, rc);
+  w->lr32 = w->alloc<float>(3 * nm, rc);
+  if (rc) {
+    delete w;
+    return h->fail(rc, "adjoint workspace allocation failed");
+  }
+  h->adj = w;
+  return LBM_OK;
+}
+
+// Copy on the handle's stream.
+int dcopy(lbm_handle* h, void* dst, const void* src, size_t bytes) {
+  return h->hip(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, h->stream), "hipMemcpyAsync");
+}
+
+int run(lbm_handle* h, const lbm_adjoint_desc* ad, double* J, double* grad) {
+  const int64_t T = ad->steps;
+  const int K = (int)std::min<int64_t>(ad->checkpoint, T);
+  const int64_t nck = (T + K - 1) / K;
+  int rc = upload(h);
+  if (!rc) rc = prologue(h);
+  if (!rc) rc = ensure_work(h, nck, K);
+  if (rc) return rc;
+  AdjWork& w = *h->adj;
+  const size_t ps = (size_t)h->pstride, nm = (size_t)h->nm, nb = h->beads.size();
+  const size_t popn = kQ * ps;
+  hipStream_t s = h->stream;
+
+  // forward run with checkpoints
+  std::vector<double> X0(3 * h->swimmers.size()), XT(X0.size());
+  rc = lbm_get_swimmer_centres(h, X0.data());
+  if (rc) return rc;
+  const int64_t t0 = h->host_step;
+  for (int64_t c = 0; c < nck; ++c) {
+    const int64_t n0 = t0 + c * K, m = std::min<int64_t>(K, T - c * K);
+    rc = dcopy(h, w.ck_pop + c * popn, h->pop[n0 & 1], sizeof(float) * popn);
+    if (!rc) rc = dcopy(h, w.ck_pos + c * 3 * nm, h->d_pos, sizeof(double) * 3 * nm);
+    if (!rc) rc = dcopy(h, w.ck_bst + c * nb, h->d_bstate, sizeof(BeadState) * nb);
+    if (!rc) rc = lbm_step(h, m);
+    if (rc) return rc;
+  }
+  rc = lbm_get_swimmer_centres(h, XT.data());
+  if (rc) return rc;
+  *J = XT[3 * ad->swimmer] - X0[3 * ad->swimmer];
+
+  // scratch views of the state for the recompute and the reverse sweep
+  Dev dS = h->dev;
+  dS.pop[0] = w.P;
+  dS.pop[1] = w.P + popn;
+  dS.F = w.F;
+  dS.u = w.u;
+  dS.stamp = w.stamp;
+  dS.step = w.step;
+  dS.U = w.U;
+  dS.near = w.near;
+  dS.near_list = w.near_list;
+  dS.near_count = w.near_count;
+  dS.overflow = w.overflow;
+  Adj a{};
+  a.lu = w.lu;
+  a.lF = w.lF;
+  a.lr = w.lr;
+  a.lr32 = w.lr32;
+  a.lfm = w.lfm;
+  a.ltmp = w.ltmp;
+  a.bsum = w.bsum;
+  a.grad = w.grad;
+  a.swimmer = ad->swimmer;
+  const size_t nsc_max = (size_t)((h->nodes + 127) / 128);
+  rc = h->hip(hipMemsetAsync(w.L, 0, sizeof(float) * 2 * popn, s), "hipMemsetAsync");
+  if (!rc) rc = h->hip(hipMemsetAsync(w.stamp, 0x80, sizeof(int) * h->ntiles, s), "hipMemsetAsync");
+  if (!rc) rc = h->hip(hipMemsetAsync(w.near, 0x80, sizeof(int) * 2 * nsc_max, s), "hipMemsetAsync");
+  if (!rc) rc = h->hip(hipMemsetAsync(w.overflow, 0, sizeof(int), s), "hipMemsetAsync");
+  if (rc) return rc;
+  launch_adj_init(dS, a, s);
+  const int nblocks = (int)((h->nodes + kScBlock - 1) / kScBlock);
+
+  for (int64_t c = nck - 1; c >= 0; --c) {
+    const int64_t n0 = t0 + c * K;
+    const int m = (int)std::min<int64_t>(K, T - c * K);
+    rc = dcopy(h, w.P + (n0 & 1) * popn, w.ck_pop + c * popn, sizeof(float) * popn);
+    if (!rc) rc = dcopy(h, w.pslab, w.ck_pos + c * 3 * nm, sizeof(double) * 3 * nm);
+    if (!rc) rc = dcopy(h, w.bslab, w.ck_bst + c * nb, sizeof(BeadState) * nb);
+    if (!rc) rc = h->hip(hipMemsetAsync(w.near_count, 0, sizeof(int) * 2, s), "hipMemsetAsync");
+    if (rc) return rc;
+    launch_set_step(w.step, n0, s);
+    // recompute: step i reads the markers of pslab[i] (copied to pslab[i+1],
+    // which advection then moves on) and the statistics of bslab[i] (the
+    // previous step's, copied to bslab[i+1] and updated there)
+    for (int i = 0; i < m; ++i) {
+      rc = dcopy(h, w.pslab + (i + 1) * 3 * nm, w.pslab + i * 3 * nm, sizeof(double) * 3 * nm);
+      if (!rc) rc = dcopy(h, w.bslab + (i + 1) * nb, w.bslab + i * nb, sizeof(BeadState) * nb);
+      if (rc) return rc;
+      Dev d = dS;
+      d.sub = i;
+      d.pos = w.pslab + (i + 1) * 3 * nm;
+      d.bstate = w.bslab + (i + 1) * nb;
+      d.fm = w.fslab + i * 3 * nm;
+      d.mom = w.mom + (size_t)i * h->nodes;
+      launch_bead_stats(d, 0, s);
+      launch_vertex_forces(d, s);
+      launch_spread(d, s);
+      launch_stream_collide_mom(d, nblocks, s);
+      d.sub = i + 1;
+      launch_interp_advance(d, s);
+    }
+    // reverse steps n = n0 + m - 1 ... n0
+    for (int i = m - 1; i >= 0; --i) {
+      const int64_t n = n0 + i;
+      Dev d = dS;
+      d.sub = i;
+      d.pos = w.pslab + i * 3 * nm;
+      d.bstate = w.bslab + (i + 1) * nb;
+      d.fm = w.fslab + i * 3 * nm;
+      launch_spread(d, s);  // F_n
+      Dev dl = d;
+      dl.fm = w.lr32;
+      dl.F = w.lu;
+      launch_spread(dl, s);  // lambda_u = S(r_n) lambda_r(n+1)
+      a.Lsrc = w.L + ((n + 1) & 1) * popn;
+      a.Ldst = w.L + (n & 1) * popn;
+      a.mom = w.mom + (size_t)i * h->nodes;
+      launch_adj_collide(d, a, nblocks, s);
+      launch_adj_gather(d, a, s);
+      launch_adj_bead(d, a, s);
+      launch_adj_tangent(d, a, s);
+    }
+    rc = h->hip(hipGetLastError(), "adjoint launch");
+    if (rc) return rc;
+  }
+  int ov = 0;
+  rc = h->hip(hipMemcpyAsync(grad, w.grad, sizeof(double) * 4, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+  if (!rc) rc = h->hip(hipMemcpyAsync(&ov, w.overflow, sizeof(int), hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+  if (!rc) rc = h->hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+  if (rc) return rc;
+  if (ov) return h->fail(LBM_EOVERFLOW, "bead region or near list overflow in the adjoint recompute");
+  return LBM_OK;
+}
+
+}  // namespace
+}  // namespace rt
+}  // namespace lbmib
+
+extern "C" {
+
+int lbm_swimmer_set_params(lbm_handle* h, int32_t swimmer, double A, double B, double alpha, double k) {
+  if (!h || swimmer < 0 || swimmer >= (int32_t)h->swimmers.size()) return LBM_EINVAL;
+  Swimmer& S = h->swimmers[swimmer];
+  S.A = A;
+  S.B = B;
+  S.alpha = alpha;
+  S.k[0] = S.k[1] = k;
+  if (!h->uploaded) return LBM_OK;
+  int rc = h->hip(hipMemcpyAsync(h->d_swimmers + swimmer, &S, sizeof(Swimmer), hipMemcpyHostToDevice, h->stream),
+                  "hipMemcpyAsync");
+  if (rc) return rc;
+  return h->hip(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+}
+
+int lbm_adjoint(lbm_handle* h, const lbm_adjoint_desc* desc, double* J, double grad[4]) {
+  if (!h || !desc || !J || !grad) return LBM_EINVAL;
+  if (desc->steps < 1 || desc->checkpoint < 1) return h->fail(LBM_EINVAL, "adjoint needs steps >= 1 and checkpoint >= 1");
+  if (desc->swimmer < 0 || desc->swimmer >= (int32_t)h->swimmers.size())
+    return h->fail(LBM_EINVAL, "adjoint objective: no such swimmer");
+  if (h->boxes.size() != 1) return h->fail(LBM_EINVAL, "adjoint: single-box handles only");
+  if (h->storage != LBM_FP32_SHIFTED) return h->fail(LBM_EINVAL, "adjoint: FP32 storage only");
+  if (h->boxes[0].forcing != kGuo) return h->fail(LBM_EINVAL, "adjoint: Guo forcing only");
+  int rc = rt::upload(h);
+  if (rc) return rc;
+  rt::Snapshot snap;
+  if (desc->rewind) {
+    rc = rt::prologue(h);
+    if (rc) return rc;
+    rt::snapshot_parts(h, snap);
+    if (hipMalloc(&snap.mem, rt::snapshot_bytes(snap)) != hipSuccess)
+      return h->fail(LBM_ENOMEM, "adjoint snapshot allocation failed");
+    rc = rt::snapshot_copy(h, snap, true);
+  }
+  if (!rc) rc = rt::run(h, desc, J, grad);
+  if (desc->rewind) {
+    const int rc2 = rt::snapshot_copy(h, snap, false);
+    if (!rc) rc = rc2;
+    (void)hipFree(snap.mem);
+  }
+  return rc;
+}
+
+}  // extern "C"

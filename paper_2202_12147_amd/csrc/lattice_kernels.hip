@@ -27,6 +27,8 @@ namespace lbmib {
 
 namespace {
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
 constexpr float kW0 = 1.0f / 3.0f;
 constexpr float kW1 = 1.0f / 18.0f;
 constexpr float kW2 = 1.0f / 36.0f;
@@ -128,7 +130,8 @@ __device__ inline int logical_block(int remap, int nblocks) {
 
 // One node of the fused step: pull, moments, forcing, BGK collision, store.
 // `forced`: read F and write u at this node (its tile is active this step).
-template <int ST>
+// MOM: also record (rho, u) of the node in d.mom.
+template <int ST, bool MOM = false>
 __device__ inline void sc_node(const Dev& d, const Box& B, int x, int y, int z, int64_t base,
                                int64_t n, bool forced) {
   using IO = PopIO<ST>;
@@ -155,6 +158,10 @@ __device__ inline void sc_node(const Dev& d, const Box& B, int x, int y, int z, 
     d.u[base] = ux;
     d.u[ps + base] = uy;
     d.u[2 * ps + base] = uz;
+  }
+  if constexpr (MOM) {
+    const f32x4 rec = {m.rho, ux, uy, uz};
+    __builtin_nontemporal_store(rec, reinterpret_cast<f32x4*>(d.mom) + base);
   }
   float ex = ux, ey = uy, ez = uz, src_a = 1.0f - 0.5f * B.omega;
   if (B.forcing == kShanChen) {
@@ -197,7 +204,7 @@ __device__ inline void sc_node(const Dev& d, const Box& B, int x, int y, int z, 
 //             tile is active.
 constexpr int kScAll = kLaunchAll, kScBulk = kLaunchBulk, kScActive = kLaunchActive;
 
-template <int ST, int BS>
+template <int ST, int BS, bool MOM = false>
 __device__ inline void sc_block(const Dev& d, int blk, int64_t n, bool bulk) {
   const int b = d.nboxes == 1 ? 0 : d.sc_block_box[blk];
   const Box B = d.boxes[b];
@@ -215,7 +222,7 @@ __device__ inline void sc_block(const Dev& d, int blk, int64_t n, bool bulk) {
     const int tile = B.tile0 + (x / kTile) + B.tx * ((y / kTile) + B.ty * (z / kTile));
     forced = d.stamp[tile] == (int)n;
   }
-  sc_node<ST>(d, B, x, y, z, B.node0 + id, n, forced);
+  sc_node<ST, MOM>(d, B, x, y, z, B.node0 + id, n, forced);
 }
 
 template <int ST, int BS, int MODE>
@@ -242,6 +249,12 @@ __global__ __launch_bounds__(BS) void k_stream_collide(Dev d, int remap, int nbl
     const int blk = logical_block(remap, nblocks);
     if (blk < nblocks) sc_block<ST, BS>(d, blk, n, false);
   }
+}
+
+// Full grid, FP32, recording (rho, u) per node (adjoint segment recompute).
+__global__ __launch_bounds__(kScBlock) void k_stream_collide_mom(Dev d) {
+  const int64_t n = *d.step + d.sub;
+  sc_block<kFp32, kScBlock, true>(d, blockIdx.x, n, false);
 }
 
 // Advance the step counter past an enqueued chunk of `count` steps.
@@ -361,7 +374,6 @@ __global__ __launch_bounds__(kScBlock) void k_conserved_final(const double* __re
 
 // Plain device copy (16 bytes per thread per iteration, grid-stride): the
 // achievable-bandwidth reference for the HBM roofline.
-typedef float f32x4 __attribute__((ext_vector_type(4)));
 __global__ __launch_bounds__(256) void k_copy(const f32x4* __restrict__ src, f32x4* __restrict__ dst,
                                               int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
@@ -421,6 +433,10 @@ void launch_stream_collide(const Dev& d, int storage, int mode, int block, int n
     launch_sc_st<kFp16>(d, mode, block, nblocks, remap, resident, ncu, s, ev0, ev1);
   else
     launch_sc_st<kFp32>(d, mode, block, nblocks, remap, resident, ncu, s, ev0, ev1);
+}
+
+void launch_stream_collide_mom(const Dev& d, int nblocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_stream_collide_mom, dim3(nblocks), dim3(kScBlock), 0, s, d);
 }
 
 void launch_tick(const Dev& d, int count, hipStream_t s) {

@@ -12,12 +12,12 @@
 
 #include "../../include/lbmib.h"
 #include "common.h"
+#include "handle.h"
 
 using namespace lbmib;
 
 namespace {
 
-constexpr int kGraphChunk = 32;  // steps per captured graph
 constexpr int kReduceParts = 1024;
 constexpr uint32_t kMagic = 0x4c424d31;  // "LBM1"
 
@@ -96,103 +96,11 @@ double dihedral(const double* x1, const double* x2, const double* x3, const doub
                     nA[0] * nB[0] + nA[1] * nB[1] + nA[2] * nB[2]);
 }
 
-template <class T>
-T* dev_alloc(size_t n, int& rc) {
-  void* p = nullptr;
-  if (n == 0) n = 1;
-  if (hipMalloc(&p, n * sizeof(T)) != hipSuccess) {
-    rc = LBM_ENOMEM;
-    return nullptr;
-  }
-  return static_cast<T*>(p);
-}
-
 const char* kErrNames[] = {"ok", "invalid argument", "out of memory", "HIP runtime error",
                            "call not allowed in this state", "non-finite conserved sums",
                            "file I/O error", "bead outgrew its reserved tile region"};
 
 }  // namespace
-
-struct lbm_handle {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  bool own_stream = false;
-  int storage = LBM_FP32_SHIFTED, width = 3;
-  float fp16_scale = 1.0f;
-  bool use_graphs = true;
-  std::string err;
-
-  // host model
-  std::vector<Box> boxes;
-  std::vector<Bead> beads;
-  std::vector<Swimmer> swimmers;
-  std::vector<double> pos0;  // [nm][3] initial marker positions
-  std::vector<int> marker_bead;
-  std::vector<int> tri;      // [ntri][3] global vertex ids
-  std::vector<double> G0;    // [ntri][3]
-  std::vector<double> hingeth0;
-  std::vector<int> hinge;    // [nh][4]
-  int nm = 0;
-  int64_t nodes = 0, pstride = 0;
-  int ntiles = 0, sc_blocks = 0, spread_blocks = 0, out_blocks = 0;
-  int sc_block = 256, sc_remap = 1, sc_resident = 0;  // stream-collide launch shape
-  int ncu = 256;                                        // compute units of the device
-  bool uploaded = false, stepped = false;
-  int64_t host_step = 0;  // steps enqueued
-
-  // device buffers
-  void* pop[2] = {nullptr, nullptr};
-  float *F = nullptr, *u = nullptr, *uout = nullptr;
-  int* stamp = nullptr;
-  Box* d_boxes = nullptr;
-  int* d_block_box = nullptr;     // 256-node block -> box
-  int* d_sc_block_box = nullptr;  // stream-collide block -> box (sized for block 128)
-  int* d_sc_box_block0 = nullptr; // first stream-collide block of each box
-  int64_t sc_table_cap = 0;
-  int64_t* d_step = nullptr;
-  double* d_pos = nullptr;
-  float *d_U = nullptr, *d_fm = nullptr;
-  Bead* d_beads = nullptr;
-  BeadState* d_bstate = nullptr;
-  Swimmer* d_swimmers = nullptr;
-  int *d_marker_bead = nullptr, *d_tri = nullptr, *d_hinge = nullptr;
-  double *d_G0 = nullptr, *d_theta0 = nullptr;
-  float *d_G0inv = nullptr, *d_A0 = nullptr, *d_idet = nullptr;
-  int *d_lane_elem = nullptr, *d_lane_v = nullptr;
-  int* d_overflow = nullptr;
-  int* d_spread_bead = nullptr;
-  int *d_near = nullptr, *d_near_list = nullptr, *d_near_count = nullptr;
-  bool need_prologue = true;
-  hipStream_t side = nullptr;      // IBM chain, forked from `stream` every step
-  std::vector<hipEvent_t> fork_join;
-  double *d_partial = nullptr, *d_out = nullptr, *d_centres = nullptr;
-  std::vector<void*> allocs;
-
-  Dev dev{};
-  hipGraphExec_t g_chunk = nullptr, g_one = nullptr;
-
-  bool timing = false;
-  double timed_ms = 0;
-  int64_t timed_launches = 0;
-  std::vector<hipEvent_t> ev_pool;
-  size_t ev_used = 0;
-
-  int fail(int code, const std::string& msg) {
-    err = msg;
-    return code;
-  }
-  int hip(hipError_t e, const char* what) {
-    if (e == hipSuccess) return LBM_OK;
-    err = std::string(what) + ": " + hipGetErrorString(e);
-    return LBM_EDEVICE;
-  }
-  template <class T>
-  T* alloc(size_t n, int& rc) {
-    T* p = dev_alloc<T>(n, rc);
-    if (p) allocs.push_back(p);
-    return p;
-  }
-};
 
 namespace {
 
@@ -766,6 +674,7 @@ int lbm_destroy(lbm_handle* h) {
   for (auto e : h->ev_pool) (void)hipEventDestroy(e);
   for (auto e : h->fork_join) (void)hipEventDestroy(e);
   if (h->side) (void)hipStreamDestroy(h->side);
+  rt::adjoint_release(h);
   for (void* p : h->allocs) (void)hipFree(p);
   if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
   delete h;
@@ -1238,14 +1147,10 @@ int lbm_set_stream_collide_launch(lbm_handle* h, int block, int xcd_remap, int r
 
 }  // extern "C"
 
-namespace {
+namespace lbmib {
+namespace rt {
 
-// Device copy of every buffer that stepping changes, for the tuner.
-struct Snapshot {
-  std::vector<std::pair<void*, size_t>> parts;
-  char* mem = nullptr;
-  int64_t host_step = 0;
-};
+// Device copy of every buffer that stepping changes (tuner, adjoint rewind).
 
 void snapshot_parts(lbm_handle* h, Snapshot& S) {
   const size_t pb = (size_t)element_bytes(h) * kQ * h->pstride;
@@ -1280,6 +1185,22 @@ int snapshot_copy(lbm_handle* h, Snapshot& S, bool take) {
   h->need_prologue = true;
   return h->hip(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
 }
+
+size_t snapshot_bytes(const Snapshot& S) {
+  size_t total = 0;
+  for (auto& p : S.parts) total += (p.second + 255) / 256 * 256;
+  return total;
+}
+
+int element_bytes(const lbm_handle* h) { return ::element_bytes(h); }
+int upload(lbm_handle* h) { return ::upload(h); }
+int prologue(lbm_handle* h) { return ::prologue(h); }
+int check_overflow(lbm_handle* h) { return ::check_overflow(h); }
+
+}  // namespace rt
+}  // namespace lbmib
+
+namespace {
 
 std::string tune_key(const lbm_handle* h) {
   char buf[128];
@@ -1326,12 +1247,11 @@ int lbm_autotune(lbm_handle* h, int32_t steps, const char* cache_path, char* rep
   for (int blk : {128, 256, 512})
     for (int remap : {0, 1})
       for (int res : residents) cands.push_back({blk, remap, res});
-  Snapshot S;
-  snapshot_parts(h, S);
-  size_t total = 0;
-  for (auto& p : S.parts) total += (p.second + 255) / 256 * 256;
+  rt::Snapshot S;
+  rt::snapshot_parts(h, S);
+  const size_t total = rt::snapshot_bytes(S);
   if (hipMalloc(&S.mem, total) != hipSuccess) return h->fail(LBM_ENOMEM, "tuner snapshot allocation failed");
-  rc = snapshot_copy(h, S, true);
+  rc = rt::snapshot_copy(h, S, true);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (!rc) rc = h->hip(hipEventCreate(&e0), "hipEventCreate");
   if (!rc) rc = h->hip(hipEventCreate(&e1), "hipEventCreate");
@@ -1343,7 +1263,7 @@ int lbm_autotune(lbm_handle* h, int32_t steps, const char* cache_path, char* rep
   for (const Cand& c : cands) {
     if (rc) break;
     rc = lbm_set_stream_collide_launch(h, c.block, c.remap, c.resident);
-    if (!rc) rc = snapshot_copy(h, S, false);
+    if (!rc) rc = rt::snapshot_copy(h, S, false);
     if (!rc) rc = lbm_step(h, 2 * kGraphChunk);
     if (!rc) rc = h->hip(hipEventRecord(e0, h->stream), "hipEventRecord");
     if (!rc) rc = lbm_step(h, steps);
@@ -1366,7 +1286,7 @@ int lbm_autotune(lbm_handle* h, int32_t steps, const char* cache_path, char* rep
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   int rc2 = lbm_set_stream_collide_launch(h, win.block, win.remap, win.resident);
-  if (!rc2) rc2 = snapshot_copy(h, S, false);
+  if (!rc2) rc2 = rt::snapshot_copy(h, S, false);
   (void)hipFree(S.mem);
   if (!rc) rc = rc2;
   if (!rc && cache_path && best < 1e300) {

@@ -29,7 +29,7 @@ SYMBOLS = [
     "lbm_save", "lbm_load", "lbm_set_kernel_timing", "lbm_kernel_time", "lbm_bytes_per_step",
     "lbm_probe_copy_bandwidth", "lbm_set_stream_collide_launch",
     "lbm_batch_create", "lbm_batch_swimmer_add", "lbm_n_boxes", "lbm_batch_get_velocity",
-    "lbm_batch_get_conserved", "lbm_autotune",
+    "lbm_batch_get_conserved", "lbm_autotune", "lbm_swimmer_set_params", "lbm_adjoint",
     "lbm_strerror", "lbm_last_error",
 ]
 
@@ -66,6 +66,11 @@ class SpringDesc(C.Structure):
 class ActuationDesc(C.Structure):
     _fields_ = [("A", C.c_double), ("B", C.c_double), ("period", C.c_double),
                 ("alpha", C.c_double), ("phi0", C.c_double)]
+
+
+class AdjointDesc(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("checkpoint", C.c_int32), ("swimmer", C.c_int32),
+                ("rewind", C.c_int32)]
 
 
 _lib = None
@@ -124,6 +129,8 @@ def load_library():
         "lbm_batch_get_velocity": (C.c_int, [vp, i32, fp, C.c_int]),
         "lbm_batch_get_conserved": (C.c_int, [vp, i32, dp]),
         "lbm_autotune": (C.c_int, [vp, i32, C.c_char_p, C.c_char_p, i32]),
+        "lbm_swimmer_set_params": (C.c_int, [vp, i32, C.c_double, C.c_double, C.c_double, C.c_double]),
+        "lbm_adjoint": (C.c_int, [vp, C.POINTER(AdjointDesc), C.POINTER(C.c_double), dp]),
         "lbm_strerror": (C.c_char_p, [C.c_int]),
         "lbm_last_error": (C.c_char_p, [vp]),
     }
@@ -336,6 +343,20 @@ class Lattice:
     def bytes_per_step(self):
         return self.lib.lbm_bytes_per_step(self.h)
 
+    def set_swimmer_params(self, swimmer, A, B, alpha, k):
+        """Driving amplitudes, phase shift and spring constant (both springs)."""
+        self._check(self.lib.lbm_swimmer_set_params(self.h, int(swimmer), float(A), float(B),
+                                                    float(alpha), float(k)))
+
+    def adjoint(self, steps, checkpoint=100, swimmer=0, rewind=False):
+        """J = x displacement of the swimmer's centre over `steps` steps and
+        dJ/d(A, B, alpha, k) from the hand-written discrete adjoint."""
+        desc = AdjointDesc(int(steps), int(checkpoint), int(swimmer), int(bool(rewind)))
+        J = C.c_double()
+        grad = np.zeros(4)
+        self._check(self.lib.lbm_adjoint(self.h, C.byref(desc), C.byref(J), _ptr(grad)))
+        return J.value, grad
+
 
 def fp16_scale_for(max_abs_dev, headroom=16.0):
     """Power-of-two scale S for FP16-shifted storage that puts the largest
@@ -429,6 +450,31 @@ def from_workload(case, storage=FP32_SHIFTED, fp16_scale=1.0, use_graphs=True, s
     for sw in case.get("swimmers", []):
         lat.add_swimmer(sw)
     return lat
+
+
+def swimmer_displacement(lattice, theta, steps, checkpoint=100, swimmer=0, rewind=True):
+    """Differentiable x displacement of a swimmer's centre over `steps` steps
+    as a function of theta = (A, B, alpha, k) (float64 tensor of 4).  The
+    forward pass sets the parameters, runs the checkpointed forward and the
+    hand-written adjoint in one library call; backward returns the stored
+    gradient times the incoming one."""
+    import torch
+
+    class _Displacement(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, th):
+            A, B, alpha, k = (float(v) for v in th.detach().cpu().tolist())
+            lattice.set_swimmer_params(swimmer, A, B, alpha, k)
+            J, grad = lattice.adjoint(steps, checkpoint, swimmer, rewind)
+            ctx.save_for_backward(torch.as_tensor(grad, dtype=th.dtype, device=th.device))
+            return torch.as_tensor(J, dtype=th.dtype, device=th.device)
+
+        @staticmethod
+        def backward(ctx, gJ):
+            (grad,) = ctx.saved_tensors
+            return gJ * grad
+
+    return _Displacement.apply(theta)
 
 
 def mlups(nodes, steps, seconds):

@@ -42,6 +42,10 @@ def test_invalid_arguments_rejected():
     assert lib.lbm_create(C.byref(ok), 1.0, 0, C.byref(bad), C.byref(h)) == -1  # scale not 2^k
     assert lib.lbm_create(None, 1.0, 0, None, C.byref(h)) == -1
     assert h.value is None
+    desc = lbmib.AdjointDesc(10, 5, 0, 0)
+    J, g = C.c_double(), (C.c_double * 4)()
+    assert lib.lbm_adjoint(None, C.byref(desc), C.byref(J), g) == -1
+    assert lib.lbm_swimmer_set_params(None, 0, 1e-3, 1e-3, 1.0, 0.01) == -1
     assert lib.lbm_strerror(-1) == b"invalid argument"
     assert lib.lbm_destroy(None) == 0
 
