@@ -117,12 +117,41 @@ def batch_section(lbmib, wl, steps=5000, warmup=200, seed=0):
             "launch": {"block": int(best[0]), "xcd_remap": int(best[1]), "resident": int(best[2])}}
 
 
+def adjoint_section(lbmib, wl):
+    """Gradient of a swimmer's displacement over one 2000-step period on the
+    96^3 adjoint workload (checkpoints every 100 steps): wall time of
+    lbm_adjoint (checkpointed forward + segment recompute + reverse sweep)
+    against the plain forward run of the same steps."""
+    case = wl.adjoint_case(reduced=False)
+    T, K = case["steps"], case["checkpoint"]
+    nodes = case["shape"][0] * case["shape"][1] * case["shape"][2]
+    lat = lbmib.from_workload(case)
+    lat.step(200)
+    lat.sync()
+    t0 = time.perf_counter()
+    lat.step(T)
+    lat.sync()
+    t_fwd = time.perf_counter() - t0
+    lat.adjoint(T, K, rewind=True)  # workspace allocation, first launches
+    t0 = time.perf_counter()
+    J, grad = lat.adjoint(T, K, rewind=True)
+    t_adj = time.perf_counter() - t0
+    return {"workload": f"adjoint {case['shape'][0]}^3, one swimmer, T={T} steps, checkpoint {K}",
+            "forward_ms": round(t_fwd * 1e3, 2), "adjoint_ms": round(t_adj * 1e3, 2),
+            "ratio": round(t_adj / t_fwd, 3),
+            "note": "adjoint_ms includes its own checkpointed forward run",
+            "adjoint_mlups": round(nodes * T / t_adj / 1e6, 1),
+            "J": J, "grad_A_B_alpha_k": [float(g) for g in grad]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="run only the adjoint section (profiling of the reverse sweep)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -133,6 +162,9 @@ def main():
     from paper_2202_12147_amd import lbmib, workloads as wl
 
     torch.cuda.set_device(0)
+    if args.adjoint_only:
+        print(json.dumps({"adjoint": adjoint_section(lbmib, wl)}), flush=True)
+        return
     case = wl.single_128(seed=0)
     nodes = case["shape"][0] * case["shape"][1] * case["shape"][2]
     stream = torch.cuda.Stream()
@@ -202,6 +234,7 @@ def main():
     out["fp16"] = fp16_section(lbmib, wl, case, args.steps, args.warmup, gmax)
     del lat
     out["batch"] = batch_section(lbmib, wl)
+    out["adjoint"] = adjoint_section(lbmib, wl)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(case)
     print(json.dumps(out), flush=True)
