@@ -14,7 +14,7 @@
 namespace lbmib {
 
 struct Adj {
-  const float* Lsrc;    // adjoint populations of step n+1, [q][pstride]
+  const float* Lsrc;    // adjoint populations of step n+1 (population block layout)
   float* Ldst;          // adjoint populations of step n
   const float4* mom;    // (rho, u_x, u_y, u_z) of step n per node
   float* lu;            // lambda_u [3][pstride] (spread of lambda_r(n+1)); tiles stamped n

@@ -53,7 +53,8 @@ __device__ inline double3 ld3(const double* p, int nm, int m) { return make_doub
 // where lambda_u is the interpolation adjoint spread onto the grid.  The
 // streamed value f_i(x) = f*_{n-1,i}(x - c_i) makes the step-(n-1) adjoint
 // at y equal lambda_f,i(y + c_i): each node pulls Lambda_i from y + c_i and
-// stores its own lambda_f (reads shifted by one element, writes coalesced).
+// stores its own lambda_f (reads shifted by one element, writes coalesced);
+// same block layout as the populations.
 __global__ __launch_bounds__(kBlock) void k_adj_collide(Dev d, Adj a) {
   const Box B = d.boxes[0];
   const int id = blockIdx.x * kBlock + threadIdx.x;
@@ -72,7 +73,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(Dev d, Adj a) {
   const int64_t ps = d.pstride, base = B.node0 + id;
   float L[kQ];
 #pragma unroll
-  for (int q = 0; q < kQ; ++q) L[q] = __builtin_nontemporal_load(a.Lsrc + q * ps + base + off[q]);
+  for (int q = 0; q < kQ; ++q) L[q] = __builtin_nontemporal_load(a.Lsrc + pop_index(q, base + off[q]));
 
   const float4 mu = a.mom[base];
   const float rho = mu.x, ux = mu.y, uy = mu.z, uz = mu.w;
@@ -149,7 +150,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(Dev d, Adj a) {
                         btx + bty,  -btx - bty, btx - bty,  bty - btx,  btx + btz,  -btx - btz, btx - btz,
                         btz - btx,  bty + btz,  -bty - btz, bty - btz,  btz - bty};
 #pragma unroll
-  for (int q = 0; q < kQ; ++q) __builtin_nontemporal_store(k1 * L[q] + a0 + cq[q], a.Ldst + q * ps + base);
+  for (int q = 0; q < kQ; ++q) __builtin_nontemporal_store(k1 * L[q] + a0 + cq[q], a.Ldst + pop_index(q, base));
 }
 
 // ---- transposed spreading and interpolation -----------------------------------------

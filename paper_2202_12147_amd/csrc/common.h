@@ -1,8 +1,11 @@
 // Internal definitions shared by the lbmib HIP translation units.
 //
 // Device layout (one allocation per array, all boxes of a batch concatenated):
-//   populations  pop[parity][q][node]   q-plane stride `pstride` elements,
-//                                       256-byte aligned; FP32 or FP16
+//   populations  pop[parity][node / 256][q][node % 256]   blocks of 256 nodes,
+//                                       the 19 populations of a block one
+//                                       after the other (pop_index); FP32 or
+//                                       FP16; pstride (node count rounded up to
+//                                       256) nodes per parity
 //   force        F[3][node]             FP32, valid only in active tiles
 //   velocity     u[3][node]             FP32, valid only in active tiles
 //   tile stamps  stamp[tile]            step index at which a tile was last
@@ -19,6 +22,15 @@ namespace lbmib {
 constexpr int kQ = 19;
 constexpr int kTile = 8;       // active-tile edge in nodes
 constexpr int kScBlock = 256;  // stream-collide threads per block
+constexpr int kPopBlock = 256; // nodes per population block
+
+// Element index of population q of global node `node`.  A wavefront's 64
+// consecutive nodes read or write one contiguous 256-byte (FP32) run per
+// population, and a 256-node block's 19 runs are adjacent, so the DRAM sees a
+// few long streams instead of 19 planes far apart.
+__host__ __device__ inline int64_t pop_index(int q, int64_t node) {
+  return (node / kPopBlock) * (int64_t)(kQ * kPopBlock) + q * kPopBlock + (node % kPopBlock);
+}
 
 enum Forcing { kGuo = 0, kShanChen = 1 };
 enum Storage { kFp32 = 0, kFp16 = 1 };

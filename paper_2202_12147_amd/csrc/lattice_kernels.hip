@@ -71,10 +71,10 @@ __device__ inline Nbr neighbours(int x, int y, int z, int nx, int ny, int nz) {
   return o;
 }
 
-// Pull the 19 deviations of node `id` (box-local) from the source planes.
+// Pull the 19 deviations of node `base` from the source populations.
 template <int ST>
-__device__ inline void pull(const typename PopIO<ST>::T* __restrict__ src, int64_t ps, int64_t base,
-                            const Nbr& o, float inv, float* g) {
+__device__ inline void pull(const typename PopIO<ST>::T* __restrict__ src, int64_t base, const Nbr& o, float inv,
+                            float* g) {
   using IO = PopIO<ST>;
   const int off[kQ] = {0,
                        o.xm, o.xp, o.ym, o.yp, o.zm, o.zp,
@@ -82,7 +82,7 @@ __device__ inline void pull(const typename PopIO<ST>::T* __restrict__ src, int64
                        o.xm + o.zm, o.xp + o.zp, o.xm + o.zp, o.xp + o.zm,
                        o.ym + o.zm, o.yp + o.zp, o.ym + o.zp, o.yp + o.zm};
 #pragma unroll
-  for (int q = 0; q < kQ; ++q) g[q] = IO::ld(src + q * ps + base + off[q], inv);
+  for (int q = 0; q < kQ; ++q) g[q] = IO::ld(src + pop_index(q, base + off[q]), inv);
 }
 
 struct Moments {
@@ -141,7 +141,7 @@ __device__ inline void sc_node(const Dev& d, const Box& B, int x, int y, int z, 
   T* __restrict__ dst = static_cast<T*>(d.pop[(n + 1) & 1]);
   const int64_t ps = d.pstride;
   float g[kQ];
-  pull<ST>(src, ps, base, o, d.fp16_inv, g);
+  pull<ST>(src, base, o, d.fp16_inv, g);
   const Moments m = moments(g);
 
   float Fx = B.gx, Fy = B.gy, Fz = B.gz;
@@ -190,7 +190,7 @@ __device__ inline void sc_node(const Dev& d, const Box& B, int x, int y, int z, 
   collide_pair(g[15], g[16], kW2, om, m.drho, m.rho, usq15, ey + ez, src_a, uy + uz, Fy + Fz, uf);
   collide_pair(g[17], g[18], kW2, om, m.drho, m.rho, usq15, ey - ez, src_a, uy - uz, Fy - Fz, uf);
 #pragma unroll
-  for (int q = 0; q < kQ; ++q) IO::st(dst + q * ps + base, g[q], d.fp16_scale);
+  for (int q = 0; q < kQ; ++q) IO::st(dst + pop_index(q, base), g[q], d.fp16_scale);
 }
 
 // Launch modes of the fused step:
@@ -295,7 +295,7 @@ __global__ __launch_bounds__(kScBlock) void k_velocity(Dev d, float* __restrict_
   const int64_t ps = d.pstride;
   const int64_t base = B.node0 + id;
   float g[kQ];
-  pull<ST>(src, ps, base, o, d.fp16_inv, g);
+  pull<ST>(src, base, o, d.fp16_inv, g);
   const Moments m = moments(g);
   float Fx = B.gx, Fy = B.gy, Fz = B.gz;
   const int tile = B.tile0 + (x / kTile) + B.tx * ((y / kTile) + B.ty * (z / kTile));
@@ -348,7 +348,7 @@ __global__ __launch_bounds__(kScBlock) void k_conserved_partial(Dev d, int box, 
          id += (int64_t)gridDim.x * kScBlock) {
       float g[kQ];
 #pragma unroll
-      for (int q = 0; q < kQ; ++q) g[q] = IO::ld(src + q * ps + B.node0 + id, d.fp16_inv);
+      for (int q = 0; q < kQ; ++q) g[q] = IO::ld(src + pop_index(q, B.node0 + id), d.fp16_inv);
       const Moments m = moments(g);
       v[0] += (double)m.drho;
       v[1] += (double)m.jx;

@@ -114,13 +114,13 @@ int reserved_tiles(double radius, int width, int T) {
 }
 
 // Host layout of population deviations: box after box, each [19][n_box];
-// device layout [q][node] with box b's nodes starting at node0_b.
+// device index pop_index(q, node0_b + n) (256-node population blocks).
 template <class F>
 void for_each_population(const lbm_handle* h, F f) {
   for (const Box& B : h->boxes) {
     const int64_t hoff = kQ * B.node0;
     for (int q = 0; q < kQ; ++q)
-      for (int64_t n = 0; n < B.n; ++n) f(hoff + q * B.n + n, q * h->pstride + B.node0 + n);
+      for (int64_t n = 0; n < B.n; ++n) f(hoff + q * B.n + n, pop_index(q, B.node0 + n));
   }
 }
 
@@ -586,7 +586,7 @@ int create_boxes(const lbm_box_desc* boxes, int nboxes, const lbm_opts* opts, lb
     h->boxes.push_back(B);
   }
   h->nodes = node0;
-  h->pstride = (node0 + 127) / 128 * 128;
+  h->pstride = (node0 + kPopBlock - 1) / kPopBlock * kPopBlock;
   h->ntiles = tile0;
   h->out_blocks = block0;
   h->sc_table_cap = sc_cap;
@@ -1039,7 +1039,7 @@ int checkpoint(lbm_handle* h, const char* path, bool save) {
   if (rc) return rc;
   FILE* f = fopen(path, save ? "wb" : "rb");
   if (!f) return h->fail(LBM_EIO, std::string("cannot open ") + path);
-  CkptHeader hd{kMagic, 2, (int32_t)h->boxes.size(), h->storage, h->width, h->nm, (int32_t)h->beads.size(),
+  CkptHeader hd{kMagic, 3, (int32_t)h->boxes.size(), h->storage, h->width, h->nm, (int32_t)h->beads.size(),
                 0, signature(h), h->nodes, h->host_step};
   if (save) {
     if (fwrite(&hd, sizeof hd, 1, f) != 1) rc = h->fail(LBM_EIO, "short write");
