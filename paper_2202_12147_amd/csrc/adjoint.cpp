@@ -6,9 +6,9 @@
 // reverse order: the segment's forward steps are recomputed from its
 // checkpoint on scratch buffers (the serial kernel order of lbm_step, so the
 // trajectory is bitwise the forward one), keeping per step the markers, the
-// bead statistics, the marker forces and (rho, u) of every node; then its
-// reverse steps run from last to first.  The handle's own state is only
-// touched by the forward run.
+// bead statistics, the marker forces, the force density with its tile stamps
+// and (rho, u) of every node; then its reverse steps run from last to first.
+// The handle's own state is only touched by the forward run.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -36,10 +36,11 @@ struct AdjWork {
   float4* mom = nullptr;        // [K][nodes]
   double* pslab = nullptr;      // [K+1][3][nm]
   BeadState* bslab = nullptr;   // [K+1][nbeads]
-  float* fslab = nullptr;       // [K][3][nm]
-  float *F = nullptr, *u = nullptr, *lu = nullptr, *lF = nullptr;  // [3][pstride]
+  float* fslab = nullptr;       // [K][3][nm] marker forces
+  float* Fslab = nullptr;       // [K][3][pstride] force density of each step (active tiles)
+  int* stslab = nullptr;        // [K][ntiles] tile stamps of each step
+  float *u = nullptr, *lu = nullptr, *lF = nullptr;  // [3][pstride]
   float* U = nullptr;           // [3][nm]
-  int* stamp = nullptr;
   int64_t* step = nullptr;
   int *near = nullptr, *near_list = nullptr, *near_count = nullptr, *overflow = nullptr;
   double *lr = nullptr, *lfm = nullptr, *ltmp = nullptr, *bsum = nullptr, *grad = nullptr;
@@ -82,12 +83,12 @@ int ensure_work(lbm_handle* h, int64_t nck, int K) {
   w->pslab = w->alloc<double>((size_t)(K + 1) * 3 * nm, rc);
   w->bslab = w->alloc<BeadState>((size_t)(K + 1) * nb, rc);
   w->fslab = w->alloc<float>((size_t)K * 3 * nm, rc);
-  w->F = w->alloc<float>(3 * ps, rc);
+  w->Fslab = w->alloc<float>((size_t)K * 3 * ps, rc);
+  w->stslab = w->alloc<int>((size_t)K * h->ntiles, rc);
   w->u = w->alloc<float>(3 * ps, rc);
   w->lu = w->alloc<float>(3 * ps, rc);
   w->lF = w->alloc<float>(3 * ps, rc);
   w->U = w->alloc<float>(3 * nm, rc);
-  w->stamp = w->alloc<int>((size_t)h->ntiles, rc);
   w->step = w->alloc<int64_t>(1, rc);
   w->near = w->alloc<int>(2 * nsc_max, rc);
   w->near_list = w->alloc<int>(2 * nsc_max, rc);
@@ -146,9 +147,7 @@ int run(lbm_handle* h, const lbm_adjoint_desc* ad, double* J, double* grad) {
   Dev dS = h->dev;
   dS.pop[0] = w.P;
   dS.pop[1] = w.P + popn;
-  dS.F = w.F;
   dS.u = w.u;
-  dS.stamp = w.stamp;
   dS.step = w.step;
   dS.U = w.U;
   dS.near = w.near;
@@ -167,7 +166,7 @@ int run(lbm_handle* h, const lbm_adjoint_desc* ad, double* J, double* grad) {
   a.swimmer = ad->swimmer;
   const size_t nsc_max = (size_t)((h->nodes + 127) / 128);
   rc = h->hip(hipMemsetAsync(w.L, 0, sizeof(float) * 2 * popn, s), "hipMemsetAsync");
-  if (!rc) rc = h->hip(hipMemsetAsync(w.stamp, 0x80, sizeof(int) * h->ntiles, s), "hipMemsetAsync");
+  if (!rc) rc = h->hip(hipMemsetAsync(w.stslab, 0x80, sizeof(int) * (size_t)K * h->ntiles, s), "hipMemsetAsync");
   if (!rc) rc = h->hip(hipMemsetAsync(w.near, 0x80, sizeof(int) * 2 * nsc_max, s), "hipMemsetAsync");
   if (!rc) rc = h->hip(hipMemsetAsync(w.overflow, 0, sizeof(int), s), "hipMemsetAsync");
   if (rc) return rc;
@@ -183,18 +182,19 @@ int run(lbm_handle* h, const lbm_adjoint_desc* ad, double* J, double* grad) {
     if (!rc) rc = h->hip(hipMemsetAsync(w.near_count, 0, sizeof(int) * 2, s), "hipMemsetAsync");
     if (rc) return rc;
     launch_set_step(w.step, n0, s);
-    // recompute: step i reads the markers of pslab[i] (copied to pslab[i+1],
-    // which advection then moves on) and the statistics of bslab[i] (the
-    // previous step's, copied to bslab[i+1] and updated there)
+    // recompute: step i reads the markers of pslab[i] and advects them into
+    // pslab[i+1]; its bead statistics go to bslab[i+1], taking the previous
+    // centres (the volume's reference point) from bslab[i]
     for (int i = 0; i < m; ++i) {
-      rc = dcopy(h, w.pslab + (i + 1) * 3 * nm, w.pslab + i * 3 * nm, sizeof(double) * 3 * nm);
-      if (!rc) rc = dcopy(h, w.bslab + (i + 1) * nb, w.bslab + i * nb, sizeof(BeadState) * nb);
-      if (rc) return rc;
       Dev d = dS;
       d.sub = i;
-      d.pos = w.pslab + (i + 1) * 3 * nm;
+      d.pos = w.pslab + i * 3 * nm;
+      d.pos_next = w.pslab + (i + 1) * 3 * nm;
+      d.bstate_prev = w.bslab + i * nb;
       d.bstate = w.bslab + (i + 1) * nb;
       d.fm = w.fslab + i * 3 * nm;
+      d.F = w.Fslab + (size_t)i * 3 * ps;
+      d.stamp = w.stslab + (size_t)i * h->ntiles;
       d.mom = w.mom + (size_t)i * h->nodes;
       launch_bead_stats(d, 0, s);
       launch_vertex_forces(d, s);
@@ -211,11 +211,12 @@ int run(lbm_handle* h, const lbm_adjoint_desc* ad, double* J, double* grad) {
       d.pos = w.pslab + i * 3 * nm;
       d.bstate = w.bslab + (i + 1) * nb;
       d.fm = w.fslab + i * 3 * nm;
-      launch_spread(d, s);  // F_n
+      d.F = w.Fslab + (size_t)i * 3 * ps;  // F_n, kept by the recompute
+      d.stamp = w.stslab + (size_t)i * h->ntiles;
       Dev dl = d;
       dl.fm = w.lr32;
       dl.F = w.lu;
-      launch_spread(dl, s);  // lambda_u = S(r_n) lambda_r(n+1)
+      launch_spread(dl, s);  // lambda_u = S(r_n) lambda_r(n+1), same tiles as F_n
       a.Lsrc = w.L + ((n + 1) & 1) * popn;
       a.Ldst = w.L + (n & 1) * popn;
       a.mom = w.mom + (size_t)i * h->nodes;

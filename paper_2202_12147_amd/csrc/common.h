@@ -136,6 +136,11 @@ struct Dev {
   // (rho, u) of every node, written by the moment-recording stream-collide
   // variant only (segment recompute of the adjoint)
   float4* mom;
+  // optional out-of-place variants (adjoint segment recompute): advection
+  // writes r + U to pos_next instead of pos, and bead statistics take the
+  // previous centres from bstate_prev instead of bstate
+  double* pos_next;
+  const BeadState* bstate_prev;
 };
 
 // Launch wrappers (defined in the .hip files).

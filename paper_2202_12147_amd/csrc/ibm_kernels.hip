@@ -146,7 +146,8 @@ __global__ __launch_bounds__(BS) void k_bead_stats(Dev d, int mark_offset) {
   // The enclosed volume 1/6 sum (r0-c).((r1-c) x (r2-c)) of a closed outward
   // surface does not depend on the reference point c; the previous step's
   // centre keeps the products small, and lets one pass reduce everything.
-  const double cx = d.bstate[b].c[0], cy = d.bstate[b].c[1], cz = d.bstate[b].c[2];
+  const BeadState* prev = d.bstate_prev ? d.bstate_prev : d.bstate;
+  const double cx = prev[b].c[0], cy = prev[b].c[1], cz = prev[b].c[2];
   double v[NV] = {0, 0, 0, 1e300, 1e300, 1e300, -1e300, -1e300, -1e300, 0};
   for (int i = threadIdx.x; i < Bd.nv; i += BS) {
     const double3 p = load_pos(d.pos, d.nm, Bd.first + i);
@@ -576,9 +577,10 @@ __global__ __launch_bounds__(kInterpBlock) void k_interp_advance(Dev d) {
     d.U[m] = ux;
     d.U[d.nm + m] = uy;
     d.U[2 * d.nm + m] = uz;
-    d.pos[m] += (double)ux;
-    d.pos[d.nm + m] += (double)uy;
-    d.pos[2 * d.nm + m] += (double)uz;
+    double* out = d.pos_next ? d.pos_next : d.pos;
+    out[m] = d.pos[m] + (double)ux;
+    out[d.nm + m] = d.pos[d.nm + m] + (double)uy;
+    out[2 * d.nm + m] = d.pos[2 * d.nm + m] + (double)uz;
   }
 }
 

@@ -372,19 +372,20 @@ __global__ __launch_bounds__(kScBlock) void k_conserved_final(const double* __re
     for (int k = 0; k < 4; ++k) out[k] = v[k];
 }
 
-// Plain device copy (16 bytes per thread per iteration, grid-stride): the
-// achievable-bandwidth reference for the HBM roofline.
+// Plain device copy, one 16-byte vector per thread over a grid that covers
+// the buffer, non-temporal loads and stores: the achievable-bandwidth
+// reference for the HBM roofline.
 __global__ __launch_bounds__(256) void k_copy(const f32x4* __restrict__ src, f32x4* __restrict__ dst,
                                               int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
-    __builtin_nontemporal_store(src[i], dst + i);
+    __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 
 }  // namespace
 
 void launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t s) {
   const int64_t n = bytes / 16;
-  const int blocks = (int)std::min<int64_t>((n + 255) / 256, 256 * 64);
+  const int blocks = (int)std::min<int64_t>((n + 255) / 256, (int64_t)1 << 30);
   hipLaunchKernelGGL(k_copy, dim3(blocks), dim3(256), 0, s, static_cast<const f32x4*>(src),
                      static_cast<f32x4*>(dst), n);
 }
