@@ -40,23 +40,37 @@ def measured_traffic():
     return int(fields["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(case, budget_s=12.0):
-    """Time the FP64 oracle on the same 128^3 workload for a few steps."""
+def cpu_baseline(case, budget_s=12.0, single_budget_s=4.0):
+    """Time the FP64 oracle on the same 128^3 workload for a few steps, on all
+    allowed host cores (at most 16) and on one."""
     from oracle import orc
     cores = min(len(os.sched_getaffinity(0)), 16)
-    orc.set_threads(cores)
-    o = orc.Oracle(case["shape"], case["tau"], case["forcing"], case["width"])
-    for sw in case["swimmers"]:
-        o.add_swimmer_desc(sw)
-    o.step(1)  # first touch
-    steps, t0 = 0, time.perf_counter()
-    while time.perf_counter() - t0 < budget_s:
-        o.step(1)
-        steps += 1
-    dt = time.perf_counter() - t0
     nodes = case["shape"][0] * case["shape"][1] * case["shape"][2]
+
+    def timed(threads, budget):
+        orc.set_threads(threads)
+        o = orc.Oracle(case["shape"], case["tau"], case["forcing"], case["width"])
+        for sw in case["swimmers"]:
+            o.add_swimmer_desc(sw)
+        o.step(1)  # first touch
+        steps, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < budget:
+            o.step(1)
+            steps += 1
+        return steps, time.perf_counter() - t0
+
+    steps, dt = timed(cores, budget_s)
+    s1, dt1 = timed(1, single_budget_s)
+    model = ""
+    try:
+        model = next(line.split(":", 1)[1].strip() for line in open("/proc/cpuinfo")
+                     if line.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
     return {"value": nodes * steps / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
-            "sample": f"{steps} FP64 steps of the same 128^3 swimmer workload (IBM included)"}
+            "sample": f"{steps} FP64 steps of the same 128^3 swimmer workload (IBM included)",
+            "single_thread_value": nodes * s1 / dt1 / 1e6, "single_thread_sample": f"{s1} steps",
+            "cpu_model": model, "comparison": "FP64 CPU oracle vs FP32 GPU"}
 
 
 def fp16_section(lbmib, wl, case, steps, warmup, gmax):
@@ -84,7 +98,8 @@ def fp16_section(lbmib, wl, case, steps, warmup, gmax):
     gbs = lat.bytes_per_step / (kms / n * 1e-3) / 1e9
     small = wl.small_case()
     disp = {}
-    for name, st, sc in (("fp32", lbmib.FP32_SHIFTED, 1.0), ("fp16", lbmib.FP16_SHIFTED, 2.0 ** 27)):
+    for name, st, sc in (("fp32", lbmib.FP32_SHIFTED, 1.0), ("fp16", lbmib.FP16_SHIFTED, 2.0 ** 27),
+                         ("fp32_plain", lbmib.FP32_PLAIN, 1.0)):
         g = lbmib.from_workload(small, storage=st, fp16_scale=sc)
         x0 = g.swimmer_centres()[0, 0]
         g.step(small["steps"])
@@ -94,7 +109,9 @@ def fp16_section(lbmib, wl, case, steps, warmup, gmax):
             "kernel_gbs": round(gbs, 1), "kernel_frac": round(gbs / PEAK_HBM_GBS, 4),
             "bytes_per_launch": lat.bytes_per_step,
             "small_case_displacement": {"fp32": disp["fp32"], "fp16": disp["fp16"],
-                                        "rel_diff": abs(disp["fp16"] - disp["fp32"]) / abs(disp["fp32"])}}
+                                        "rel_diff": abs(disp["fp16"] - disp["fp32"]) / abs(disp["fp32"]),
+                                        "fp32_plain": disp["fp32_plain"],
+                                        "plain_rel_diff": abs(disp["fp32_plain"] - disp["fp32"]) / abs(disp["fp32"])}}
 
 
 def batch_section(lbmib, wl, steps=5000, warmup=200, seed=0):
@@ -142,6 +159,25 @@ def adjoint_section(lbmib, wl):
             "note": "adjoint_ms includes its own checkpointed forward run",
             "adjoint_mlups": round(nodes * T / t_adj / 1e6, 1),
             "J": J, "grad_A_B_alpha_k": [float(g) for g in grad]}
+
+
+def paper_box_section(lbmib, wl, steps=500, warmup=50):
+    """Throughput on the paper's 1024x256x256 box (67.1 M nodes, 10.2 GB of
+    FP32 populations per step) with one radius-5 swimmer."""
+    case = wl.paper_box()
+    nodes = case["shape"][0] * case["shape"][1] * case["shape"][2]
+    lat = lbmib.from_workload(case)
+    lat.autotune(16)
+    lat.step(warmup)
+    lat.sync()
+    t0 = time.perf_counter()
+    lat.step(steps)
+    lat.sync()
+    dt = time.perf_counter() - t0
+    return {"workload": case["name"], "nodes": nodes, "markers": lat.n_markers, "steps": steps,
+            "value": round(nodes * steps / dt / 1e6, 1), "unit": "MLUPS",
+            "ms_per_step": round(dt / steps * 1e3, 4),
+            "step_gbs": round(lat.bytes_per_step / (dt / steps) / 1e9, 1)}
 
 
 def main():
@@ -235,6 +271,7 @@ def main():
     del lat
     out["batch"] = batch_section(lbmib, wl)
     out["adjoint"] = adjoint_section(lbmib, wl)
+    out["paper_box"] = paper_box_section(lbmib, wl)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(case)
     print(json.dumps(out), flush=True)

@@ -59,10 +59,12 @@ extern "C" {
  * physical velocity is rho u = sum f c + F/2 (Sec. 2.1). */
 typedef enum { LBM_GUO = 0, LBM_SHAN_CHEN = 1 } lbm_forcing;
 
-/* Population storage on the device.  Both store the deviation g = f - w from
- * the rest state and compute in FP32; FP16_SHIFTED stores g * scale rounded
- * to nearest-even half precision. */
-typedef enum { LBM_FP32_SHIFTED = 0, LBM_FP16_SHIFTED = 1 } lbm_storage;
+/* Population storage on the device; arithmetic is FP32 in all three.  The
+ * shifted forms store the deviation g = f - w from the rest state;
+ * FP16_SHIFTED stores g * scale rounded to nearest-even half precision.
+ * FP32_PLAIN stores f itself, rounded at the scale of the weights (~1/3), a
+ * reference that shows the precision the shift recovers. */
+typedef enum { LBM_FP32_SHIFTED = 0, LBM_FP16_SHIFTED = 1, LBM_FP32_PLAIN = 2 } lbm_storage;
 
 /* ---- descriptors ---------------------------------------------------------- */
 typedef struct {

@@ -33,7 +33,7 @@ __host__ __device__ inline int64_t pop_index(int q, int64_t node) {
 }
 
 enum Forcing { kGuo = 0, kShanChen = 1 };
-enum Storage { kFp32 = 0, kFp16 = 1 };
+enum Storage { kFp32 = 0, kFp16 = 1, kFp32Plain = 2 };
 enum ScLaunch { kLaunchAll = 0, kLaunchBulk = 1, kLaunchActive = 2 };
 
 // One periodic box.  A single-box handle has exactly one.

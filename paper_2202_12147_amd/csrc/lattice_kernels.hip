@@ -9,7 +9,8 @@
 //
 // Storage holds g_i = f_i - w_i (deviation from the rest state), so the
 // O(1e-5) flow signal is not swamped by the O(1/3) weights in FP32; FP16
-// storage holds g_i * S rounded to nearest even.  Arithmetic is FP32.
+// storage holds g_i * S rounded to nearest even; the unshifted reference
+// storage holds f_i.  Arithmetic is FP32 on g in all three.
 //
 // Streaming is "pull": node x gathers g*_i(x - c_i) from the source parity and
 // writes its 19 post-collision values to the same node of the other parity,
@@ -36,22 +37,32 @@ constexpr float kW2 = 1.0f / 36.0f;
 template <int ST>
 struct PopIO;
 
+__device__ constexpr float weight(int q) { return q == 0 ? kW0 : (q < 7 ? kW1 : kW2); }
+
+// Load / store of population q as the deviation g = f - w_q.
 template <>
 struct PopIO<kFp32> {
   using T = float;
-  __device__ static inline float ld(const float* p, float) { return __builtin_nontemporal_load(p); }
-  __device__ static inline void st(float* p, float v, float) { __builtin_nontemporal_store(v, p); }
+  __device__ static inline float ld(const float* p, int, float) { return __builtin_nontemporal_load(p); }
+  __device__ static inline void st(float* p, int, float v, float) { __builtin_nontemporal_store(v, p); }
 };
 
 template <>
 struct PopIO<kFp16> {
   using T = __half;
-  __device__ static inline float ld(const __half* p, float inv) {
-    return __half2float(*p) * inv;
+  __device__ static inline float ld(const __half* p, int, float inv) { return __half2float(*p) * inv; }
+  __device__ static inline void st(__half* p, int, float v, float scale) { *p = __float2half_rn(v * scale); }
+};
+
+// Unshifted storage of f itself (rounded at the scale of w_q ~ 1/3): the
+// reference that shows what the shifted forms gain.
+template <>
+struct PopIO<kFp32Plain> {
+  using T = float;
+  __device__ static inline float ld(const float* p, int q, float) {
+    return __builtin_nontemporal_load(p) - weight(q);
   }
-  __device__ static inline void st(__half* p, float v, float scale) {
-    *p = __float2half_rn(v * scale);
-  }
+  __device__ static inline void st(float* p, int q, float v, float) { __builtin_nontemporal_store(v + weight(q), p); }
 };
 
 // Offsets (in nodes, periodic wrap folded in) of the six face neighbours.
@@ -82,7 +93,7 @@ __device__ inline void pull(const typename PopIO<ST>::T* __restrict__ src, int64
                        o.xm + o.zm, o.xp + o.zp, o.xm + o.zp, o.xp + o.zm,
                        o.ym + o.zm, o.yp + o.zp, o.ym + o.zp, o.yp + o.zm};
 #pragma unroll
-  for (int q = 0; q < kQ; ++q) g[q] = IO::ld(src + pop_index(q, base + off[q]), inv);
+  for (int q = 0; q < kQ; ++q) g[q] = IO::ld(src + pop_index(q, base + off[q]), q, inv);
 }
 
 struct Moments {
@@ -190,7 +201,7 @@ __device__ inline void sc_node(const Dev& d, const Box& B, int x, int y, int z, 
   collide_pair(g[15], g[16], kW2, om, m.drho, m.rho, usq15, ey + ez, src_a, uy + uz, Fy + Fz, uf);
   collide_pair(g[17], g[18], kW2, om, m.drho, m.rho, usq15, ey - ez, src_a, uy - uz, Fy - Fz, uf);
 #pragma unroll
-  for (int q = 0; q < kQ; ++q) IO::st(dst + pop_index(q, base), g[q], d.fp16_scale);
+  for (int q = 0; q < kQ; ++q) IO::st(dst + pop_index(q, base), q, g[q], d.fp16_scale);
 }
 
 // Launch modes of the fused step:
@@ -348,7 +359,7 @@ __global__ __launch_bounds__(kScBlock) void k_conserved_partial(Dev d, int box, 
          id += (int64_t)gridDim.x * kScBlock) {
       float g[kQ];
 #pragma unroll
-      for (int q = 0; q < kQ; ++q) g[q] = IO::ld(src + pop_index(q, B.node0 + id), d.fp16_inv);
+      for (int q = 0; q < kQ; ++q) g[q] = IO::ld(src + pop_index(q, B.node0 + id), q, d.fp16_inv);
       const Moments m = moments(g);
       v[0] += (double)m.drho;
       v[1] += (double)m.jx;
@@ -432,6 +443,8 @@ void launch_stream_collide(const Dev& d, int storage, int mode, int block, int n
                            int resident, int ncu, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   if (storage == kFp16)
     launch_sc_st<kFp16>(d, mode, block, nblocks, remap, resident, ncu, s, ev0, ev1);
+  else if (storage == kFp32Plain)
+    launch_sc_st<kFp32Plain>(d, mode, block, nblocks, remap, resident, ncu, s, ev0, ev1);
   else
     launch_sc_st<kFp32>(d, mode, block, nblocks, remap, resident, ncu, s, ev0, ev1);
 }
@@ -448,6 +461,8 @@ void launch_velocity(const Dev& d, int storage, int nblocks, float* u_out, float
                      hipStream_t s) {
   if (storage == kFp16)
     hipLaunchKernelGGL(k_velocity<kFp16>, dim3(nblocks), dim3(kScBlock), 0, s, d, u_out, rho_out);
+  else if (storage == kFp32Plain)
+    hipLaunchKernelGGL(k_velocity<kFp32Plain>, dim3(nblocks), dim3(kScBlock), 0, s, d, u_out, rho_out);
   else
     hipLaunchKernelGGL(k_velocity<kFp32>, dim3(nblocks), dim3(kScBlock), 0, s, d, u_out, rho_out);
 }
@@ -456,6 +471,8 @@ void launch_conserved(const Dev& d, int storage, int box, double* partial, int n
                       hipStream_t s) {
   if (storage == kFp16)
     hipLaunchKernelGGL(k_conserved_partial<kFp16>, dim3(nparts), dim3(kScBlock), 0, s, d, box, partial);
+  else if (storage == kFp32Plain)
+    hipLaunchKernelGGL(k_conserved_partial<kFp32Plain>, dim3(nparts), dim3(kScBlock), 0, s, d, box, partial);
   else
     hipLaunchKernelGGL(k_conserved_partial<kFp32>, dim3(nparts), dim3(kScBlock), 0, s, d, box, partial);
   hipLaunchKernelGGL(k_conserved_final, dim3(1), dim3(kScBlock), 0, s, partial, nparts, out);

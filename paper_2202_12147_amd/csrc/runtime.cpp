@@ -106,6 +106,9 @@ namespace {
 
 int element_bytes(const lbm_handle* h) { return h->storage == LBM_FP16_SHIFTED ? 2 : 4; }
 
+// D3Q19 weight of population q in FP32 (the rounding the device uses).
+float lattice_weight(int q) { return q == 0 ? 1.0f / 3.0f : (q < 7 ? 1.0f / 18.0f : 1.0f / 36.0f); }
+
 // Candidate tiles reserved per axis for a bead: the node span of its stencils
 // with 25% room for deformation, in tiles, for any alignment.
 int reserved_tiles(double radius, int width, int T) {
@@ -120,7 +123,7 @@ void for_each_population(const lbm_handle* h, F f) {
   for (const Box& B : h->boxes) {
     const int64_t hoff = kQ * B.node0;
     for (int q = 0; q < kQ; ++q)
-      for (int64_t n = 0; n < B.n; ++n) f(hoff + q * B.n + n, pop_index(q, B.node0 + n));
+      for (int64_t n = 0; n < B.n; ++n) f(hoff + q * B.n + n, pop_index(q, B.node0 + n), q);
   }
 }
 
@@ -527,7 +530,8 @@ int create_boxes(const lbm_box_desc* boxes, int nboxes, const lbm_opts* opts, lb
   if (total >= (int64_t)1 << 31) return LBM_EINVAL;
   lbm_opts o{LBM_FP32_SHIFTED, 3, 1.0f, 1, nullptr};
   if (opts) o = *opts;
-  if (o.storage != LBM_FP32_SHIFTED && o.storage != LBM_FP16_SHIFTED) return LBM_EINVAL;
+  if (o.storage != LBM_FP32_SHIFTED && o.storage != LBM_FP16_SHIFTED && o.storage != LBM_FP32_PLAIN)
+    return LBM_EINVAL;
   if (o.delta_width < 2 || o.delta_width > 4) return LBM_EINVAL;
   if (o.fp16_scale == 0.0f) o.fp16_scale = 1.0f;
   {
@@ -611,8 +615,16 @@ int create_boxes(const lbm_box_desc* boxes, int nboxes, const lbm_opts* opts, lb
     lbm_destroy(h);
     return LBM_ENOMEM;
   }
-  rc = h->hip(hipMemset(h->pop[0], 0, eb * kQ * h->pstride), "hipMemset");
-  if (!rc) rc = h->hip(hipMemset(h->pop[1], 0, eb * kQ * h->pstride), "hipMemset");
+  if (h->storage == LBM_FP32_PLAIN) {
+    // rest state f = w (the shifted forms store g = 0)
+    std::vector<float> rest(kQ * (size_t)h->pstride);
+    for (int64_t i = 0; i < (int64_t)rest.size(); ++i) rest[i] = lattice_weight((int)((i / kPopBlock) % kQ));
+    rc = h->hip(hipMemcpy(h->pop[0], rest.data(), rest.size() * 4, hipMemcpyHostToDevice), "hipMemcpy");
+    if (!rc) rc = h->hip(hipMemcpy(h->pop[1], rest.data(), rest.size() * 4, hipMemcpyHostToDevice), "hipMemcpy");
+  } else {
+    rc = h->hip(hipMemset(h->pop[0], 0, eb * kQ * h->pstride), "hipMemset");
+    if (!rc) rc = h->hip(hipMemset(h->pop[1], 0, eb * kQ * h->pstride), "hipMemset");
+  }
   if (!rc) rc = h->hip(hipMemset(h->F, 0, sizeof(float) * 3 * h->pstride), "hipMemset");
   if (!rc) rc = h->hip(hipMemset(h->u, 0, sizeof(float) * 3 * h->pstride), "hipMemset");
   if (!rc) rc = h->hip(hipMemset(h->stamp, 0x80, sizeof(int) * h->ntiles), "hipMemset");
@@ -979,13 +991,18 @@ int lbm_set_populations(lbm_handle* h, const double* dev) {
   const int cur = 0;  // step counter is 0 before stepping
   if (h->storage == LBM_FP16_SHIFTED) {
     std::vector<_Float16> buf(kQ * (size_t)h->pstride, (_Float16)0);
-    for_each_population(h, [&](int64_t hi, int64_t di) {
+    for_each_population(h, [&](int64_t hi, int64_t di, int) {
       buf[di] = (_Float16)((float)dev[hi] * h->fp16_scale);
     });
     return h->hip(hipMemcpy(h->pop[cur], buf.data(), buf.size() * 2, hipMemcpyHostToDevice), "hipMemcpy");
   }
   std::vector<float> buf(kQ * (size_t)h->pstride, 0.0f);
-  for_each_population(h, [&](int64_t hi, int64_t di) { buf[di] = (float)dev[hi]; });
+  if (h->storage == LBM_FP32_PLAIN)
+    for (int64_t i = 0; i < (int64_t)buf.size(); ++i) buf[i] = lattice_weight((int)((i / kPopBlock) % kQ));
+  if (h->storage == LBM_FP32_PLAIN)
+    for_each_population(h, [&](int64_t hi, int64_t di, int q) { buf[di] = (float)(lattice_weight(q) + dev[hi]); });
+  else
+    for_each_population(h, [&](int64_t hi, int64_t di, int) { buf[di] = (float)dev[hi]; });
   return h->hip(hipMemcpy(h->pop[cur], buf.data(), buf.size() * 4, hipMemcpyHostToDevice), "hipMemcpy");
 }
 
@@ -998,7 +1015,7 @@ int lbm_get_populations(lbm_handle* h, double* dev) {
     std::vector<_Float16> buf(kQ * (size_t)h->pstride);
     rc = h->hip(hipMemcpy(buf.data(), h->pop[cur], buf.size() * 2, hipMemcpyDeviceToHost), "hipMemcpy");
     if (rc) return rc;
-    for_each_population(h, [&](int64_t hi, int64_t di) {
+    for_each_population(h, [&](int64_t hi, int64_t di, int) {
       dev[hi] = (double)((float)buf[di] / h->fp16_scale);
     });
     return LBM_OK;
@@ -1006,7 +1023,12 @@ int lbm_get_populations(lbm_handle* h, double* dev) {
   std::vector<float> buf(kQ * (size_t)h->pstride);
   rc = h->hip(hipMemcpy(buf.data(), h->pop[cur], buf.size() * 4, hipMemcpyDeviceToHost), "hipMemcpy");
   if (rc) return rc;
-  for_each_population(h, [&](int64_t hi, int64_t di) { dev[hi] = (double)buf[di]; });
+  if (h->storage == LBM_FP32_PLAIN)
+    for_each_population(h, [&](int64_t hi, int64_t di, int q) {
+      dev[hi] = (double)buf[di] - (double)lattice_weight(q);
+    });
+  else
+    for_each_population(h, [&](int64_t hi, int64_t di, int) { dev[hi] = (double)buf[di]; });
   return LBM_OK;
 }
 

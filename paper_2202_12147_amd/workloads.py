@@ -114,6 +114,17 @@ def adjoint_case(reduced=False):
                 swimmers=[swimmer(mid, sp, A=1e-3, T=2000.0, alpha=math.pi / 3)])
 
 
+def paper_box():
+    """The paper's box (Sec. 3): 1024x256x256, tau 1, 3-point kernel, one
+    swimmer of radius-5 beads (1280 triangles) with rest length 36, spring
+    constant 0.02, amplitudes A = B = 5e-3, alpha = pi/2, period 2e4; for
+    throughput (a few hundred steps)."""
+    return dict(name="paper box 1024x256x256", shape=(1024, 256, 256), tau=1.0, forcing=GUO, width=3,
+                steps=500,
+                swimmers=[swimmer((512, 128, 128), 36.0, radius=5.0, level=3, k=0.02, A=5e-3, T=2e4,
+                                  alpha=math.pi / 2)])
+
+
 def random_deviation(shape, seed=0, eps=1e-4, modes=3):
     """Smooth random population deviations [19, z, y, x]: a few random Fourier
     modes per population, amplitude ``eps``."""
