@@ -188,6 +188,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="run only the adjoint section (profiling of the reverse sweep)")
+    ap.add_argument("--main-only", action="store_true",
+                    help="skip the fp16, batch, adjoint and paper-box sections (counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -265,13 +267,14 @@ def main():
                      "frac_of_copy_probe": round(achieved / copy_gbs, 4)},
     }
     lat.set_stream_collide_launch(256, True, 0)
-    import numpy as np
-    gmax = float(np.abs(lat.populations()).max())
-    out["fp16"] = fp16_section(lbmib, wl, case, args.steps, args.warmup, gmax)
-    del lat
-    out["batch"] = batch_section(lbmib, wl)
-    out["adjoint"] = adjoint_section(lbmib, wl)
-    out["paper_box"] = paper_box_section(lbmib, wl)
+    if not args.main_only:
+        import numpy as np
+        gmax = float(np.abs(lat.populations()).max())
+        out["fp16"] = fp16_section(lbmib, wl, case, args.steps, args.warmup, gmax)
+        del lat
+        out["batch"] = batch_section(lbmib, wl)
+        out["adjoint"] = adjoint_section(lbmib, wl)
+        out["paper_box"] = paper_box_section(lbmib, wl)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(case)
     print(json.dumps(out), flush=True)

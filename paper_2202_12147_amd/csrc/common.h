@@ -22,7 +22,7 @@ namespace lbmib {
 constexpr int kQ = 19;
 constexpr int kTile = 8;       // active-tile edge in nodes
 constexpr int kScBlock = 256;  // stream-collide threads per block
-constexpr int kPopBlock = 256; // nodes per population block
+constexpr int kPopBlock = 256; // nodes per population block (a power of two: shifts and masks)
 
 // Element index of population q of global node `node`.  A wavefront's 64
 // consecutive nodes read or write one contiguous 256-byte (FP32) run per

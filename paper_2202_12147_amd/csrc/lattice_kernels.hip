@@ -92,8 +92,16 @@ __device__ inline void pull(const typename PopIO<ST>::T* __restrict__ src, int64
                        o.xm + o.ym, o.xp + o.yp, o.xm + o.yp, o.xp + o.ym,
                        o.xm + o.zm, o.xp + o.zp, o.xm + o.zp, o.xp + o.zm,
                        o.ym + o.zm, o.yp + o.zp, o.ym + o.zp, o.yp + o.zm};
+  // addresses relative to the node's own population block: 32-bit lane and
+  // population offsets, one 64-bit multiply-add per population for the block
+  const typename PopIO<ST>::T* bp = src + (base / kPopBlock) * (int64_t)(kQ * kPopBlock);
+  const int lane = (int)(base % kPopBlock);
 #pragma unroll
-  for (int q = 0; q < kQ; ++q) g[q] = IO::ld(src + pop_index(q, base + off[q]), q, inv);
+  for (int q = 0; q < kQ; ++q) {
+    const int rel = lane + off[q];
+    const int db = rel >> 8;  // floor(rel / kPopBlock): arithmetic shift, kPopBlock = 256
+    g[q] = IO::ld(bp + (int64_t)db * (kQ * kPopBlock) + (q * kPopBlock + (rel & (kPopBlock - 1))), q, inv);
+  }
 }
 
 struct Moments {
@@ -200,8 +208,9 @@ __device__ inline void sc_node(const Dev& d, const Box& B, int x, int y, int z, 
   collide_pair(g[13], g[14], kW2, om, m.drho, m.rho, usq15, ex - ez, src_a, ux - uz, Fx - Fz, uf);
   collide_pair(g[15], g[16], kW2, om, m.drho, m.rho, usq15, ey + ez, src_a, uy + uz, Fy + Fz, uf);
   collide_pair(g[17], g[18], kW2, om, m.drho, m.rho, usq15, ey - ez, src_a, uy - uz, Fy - Fz, uf);
+  T* const bq = dst + (base / kPopBlock) * (int64_t)(kQ * kPopBlock) + (int)(base % kPopBlock);
 #pragma unroll
-  for (int q = 0; q < kQ; ++q) IO::st(dst + pop_index(q, base), q, g[q], d.fp16_scale);
+  for (int q = 0; q < kQ; ++q) IO::st(bq + q * kPopBlock, q, g[q], d.fp16_scale);
 }
 
 // Launch modes of the fused step:
@@ -350,7 +359,6 @@ __global__ __launch_bounds__(kScBlock) void k_conserved_partial(Dev d, int box, 
   using T = typename IO::T;
   const int64_t c = *d.step;
   const T* src = static_cast<const T*>(d.pop[c & 1]);
-  const int64_t ps = d.pstride;
   double v[4] = {0, 0, 0, 0};
   for (int b = 0; b < d.nboxes; ++b) {
     if (box >= 0 && b != box) continue;
