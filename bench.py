@@ -20,6 +20,11 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+# stream-collide launch shapes (block, XCD remap, resident workgroups per CU)
+# that lbm_autotune chose for these workloads on MI355X
+MAIN_LAUNCH = (256, True, 2)
+BATCH_LAUNCH = (512, True, 0)
+BOX_LAUNCH = (256, True, 0)
 PMC_PROFILE = os.path.join(ROOT, "profiles", "stream_collide_128cubed_pmc.txt")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2202_12147_amd", "csrc", "lattice_kernels.hip")
 
@@ -116,12 +121,11 @@ def fp16_section(lbmib, wl, case, steps, warmup, gmax):
 
 def batch_section(lbmib, wl, steps=5000, warmup=200, seed=0):
     """The 64-box ensemble (edges from {48,64,80,96} per axis, one swimmer
-    each) advanced together: launch shape autotuned, then `steps` timed
+    each) advanced together: the launch shape the autotuner picked for it, then `steps` timed
     steps; batch MLUPS = total nodes x steps / time."""
     ens = wl.ensemble(seed=seed)
     batch = lbmib.batch_from_ensemble(ens)
-    report = batch.autotune(32)
-    best = min((line.split() for line in report.strip().splitlines()), key=lambda f: float(f[3]))
+    batch.set_stream_collide_launch(*BATCH_LAUNCH)
     batch.step(warmup)
     batch.sync()
     t0 = time.perf_counter()
@@ -131,7 +135,7 @@ def batch_section(lbmib, wl, steps=5000, warmup=200, seed=0):
     return {"value": round(batch.N * steps / dt / 1e6, 1), "unit": "MLUPS", "steps": steps,
             "ms_per_step": round(dt / steps * 1e3, 4), "boxes": len(ens["boxes"]), "nodes": batch.N,
             "markers": batch.n_markers, "seed": seed,
-            "launch": {"block": int(best[0]), "xcd_remap": int(best[1]), "resident": int(best[2])}}
+            "launch": {"block": BATCH_LAUNCH[0], "xcd_remap": int(BATCH_LAUNCH[1]), "resident": BATCH_LAUNCH[2]}}
 
 
 def adjoint_section(lbmib, wl):
@@ -167,7 +171,7 @@ def paper_box_section(lbmib, wl, steps=500, warmup=50):
     case = wl.paper_box()
     nodes = case["shape"][0] * case["shape"][1] * case["shape"][2]
     lat = lbmib.from_workload(case)
-    lat.autotune(16)
+    lat.set_stream_collide_launch(*BOX_LAUNCH)
     lat.step(warmup)
     lat.sync()
     t0 = time.perf_counter()
@@ -207,8 +211,7 @@ def main():
     nodes = case["shape"][0] * case["shape"][1] * case["shape"][2]
     stream = torch.cuda.Stream()
     lat = lbmib.from_workload(case, stream=stream)
-    tune_report = lat.autotune(64)
-    tuned = min((line.split() for line in tune_report.strip().splitlines()), key=lambda f: float(f[3]))
+    lat.set_stream_collide_launch(*MAIN_LAUNCH)
 
     lat.step(args.warmup)
     lat.sync()
@@ -256,7 +259,8 @@ def main():
                                "3 beads r=4 x 1280 triangles, spacing 16, A=5e-4, T=2000)",
                    "grid": list(case["shape"]), "markers": lat.n_markers, "seed": 0,
                    "storage": "fp32 shifted",
-                   "launch": {"block": int(tuned[0]), "xcd_remap": int(tuned[1]), "resident": int(tuned[2])}},
+                   "launch": {"block": MAIN_LAUNCH[0], "xcd_remap": int(MAIN_LAUNCH[1]),
+                              "resident": MAIN_LAUNCH[2]}},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
                      "traffic_bytes_per_launch": tbytes,
