@@ -13,6 +13,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <map>
 #include <vector>
 
 #include "adjoint.h"
@@ -42,11 +43,26 @@ struct AdjWork {
   float *u = nullptr, *lu = nullptr, *lF = nullptr;  // [3][pstride]
   float* U = nullptr;           // [3][nm]
   int64_t* step = nullptr;
-  int *near = nullptr, *near_list = nullptr, *near_count = nullptr, *overflow = nullptr;
+  int* overflow = nullptr;
+  // near-block marks of every segment step (blocks of kScBlock nodes): flags
+  // [K+1][2][nsc], lists [K+1][2][max_near], counts [K+1][2]; entry i holds
+  // the marks step i's launches read (made by step i-1's bead statistics)
+  int nsc = 0, max_near = 0;
+  int *nflag = nullptr, *nlist = nullptr, *ncount = nullptr, *count_sink = nullptr;
+  BeadState* bsink = nullptr;   // bead statistics of the segment-start marking
+  hipStream_t side = nullptr;
+  hipEvent_t ev[10] = {};
+  std::map<int64_t, hipGraphExec_t> graphs;  // segment graphs by 2 * length + parity
   double *lr = nullptr, *lfm = nullptr, *ltmp = nullptr, *bsum = nullptr, *grad = nullptr;
   float* lr32 = nullptr;
 
   ~AdjWork() {
+    if (side) (void)hipStreamSynchronize(side);
+    for (auto& kv : graphs)
+      if (kv.second) (void)hipGraphExecDestroy(kv.second);
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+    if (side) (void)hipStreamDestroy(side);
     for (void* p : allocs) (void)hipFree(p);
   }
   template <class T>
@@ -71,7 +87,6 @@ int ensure_work(lbm_handle* h, int64_t nck, int K) {
   auto* w = new AdjWork;
   int rc = LBM_OK;
   const size_t ps = (size_t)h->pstride, nm = (size_t)h->nm, nb = h->beads.size();
-  const size_t nsc_max = (size_t)((h->nodes + 127) / 128);
   w->nck = nck;
   w->K = K;
   w->ck_pop = w->alloc<float>((size_t)nck * kQ * ps, rc);
@@ -90,9 +105,22 @@ int ensure_work(lbm_handle* h, int64_t nck, int K) {
   w->lF = w->alloc<float>(3 * ps, rc);
   w->U = w->alloc<float>(3 * nm, rc);
   w->step = w->alloc<int64_t>(1, rc);
-  w->near = w->alloc<int>(2 * nsc_max, rc);
-  w->near_list = w->alloc<int>(2 * nsc_max, rc);
-  w->near_count = w->alloc<int>(2, rc);
+  // near-block bound of the scratch launches (as set_near_bounds, blocks of kScBlock)
+  w->nsc = (int)((h->nodes + kScBlock - 1) / kScBlock);
+  int64_t mx = 0;
+  for (const Bead& b : h->beads) {
+    const Box& B = h->boxes[b.box];
+    const int64_t sx = std::min<int64_t>(b.tiles_x * kTile + 4, B.nx);
+    const int64_t sy = std::min<int64_t>(b.tiles_y * kTile + 4, B.ny);
+    const int64_t sz = std::min<int64_t>(b.tiles_z * kTile + 4, B.nz);
+    mx += sy * sz * (sx / kScBlock + 2);
+  }
+  w->max_near = (int)std::max<int64_t>(1, std::min<int64_t>(mx, w->nsc));
+  w->nflag = w->alloc<int>((size_t)(K + 1) * 2 * w->nsc, rc);
+  w->nlist = w->alloc<int>((size_t)(K + 1) * 2 * w->max_near, rc);
+  w->ncount = w->alloc<int>((size_t)(K + 1) * 2, rc);
+  w->count_sink = w->alloc<int>(2, rc);
+  w->bsink = w->alloc<BeadState>(nb, rc);
   w->overflow = w->alloc<int>(1, rc);
   w->lr = w->alloc<double>(3 * nm, rc);
   w->lfm = w->alloc<double>(3 * nm, rc);
@@ -100,12 +128,167 @@ int ensure_work(lbm_handle* h, int64_t nck, int K) {
   w->bsum = w->alloc<double>(4 * nb, rc);
   w->grad = w->alloc<double>(4, rc);
   w->lr32 = w->alloc<float>(3 * nm, rc);
+  if (!rc) rc = h->hip(hipStreamCreate(&w->side), "hipStreamCreate");
+  for (hipEvent_t& e : w->ev)
+    if (!rc) rc = h->hip(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreateWithFlags");
   if (rc) {
     delete w;
     return h->fail(rc, "adjoint workspace allocation failed");
   }
   h->adj = w;
   return LBM_OK;
+}
+
+// The scratch view reading (and, for bead statistics, writing) the near-block
+// marks of segment step i.
+Dev near_view(const Dev& base, const AdjWork& w, int i) {
+  Dev d = base;
+  d.near = w.nflag + (size_t)i * 2 * w.nsc;
+  d.near_list = w.nlist + (size_t)i * 2 * w.max_near;
+  d.near_count = w.ncount + (size_t)i * 2;
+  return d;
+}
+
+Dev with_near(Dev d, const Dev& n) {
+  d.near = n.near;
+  d.near_list = n.near_list;
+  d.near_count = n.near_count;
+  return d;
+}
+
+// Advection of segment step i: markers of pslab[i] into pslab[i+1]; the
+// near-count reset of the advection kernel goes to a sink (every entry's
+// counts are cleared at segment start).
+Dev advect_view(const Dev& base, const AdjWork& w, int i, size_t nm) {
+  Dev d = base;
+  d.sub = i + 1;
+  d.pos = w.pslab + i * 3 * nm;
+  d.pos_next = w.pslab + (i + 1) * 3 * nm;
+  d.near_count = w.count_sink;
+  return d;
+}
+
+// Everything of one segment after its checkpoint is in place: near marks of
+// its first step, the recompute, the reverse sweep.  Depends on the segment
+// only through its length m and the parity par of its first step.
+void enqueue_segment(lbm_handle* h, AdjWork& w, const Dev& dS, Adj a, int m, int par, int nblocks) {
+  const size_t ps = (size_t)h->pstride, nm = (size_t)h->nm, nb = h->beads.size();
+  const size_t popn = kQ * ps;
+  hipStream_t s = h->stream;
+  // near marks of the segment's first step from the checkpoint's markers (into entry 0),
+  // bead statistics discarded
+  {
+    Dev d = near_view(dS, w, 0);
+    d.pos = w.pslab;
+    d.bstate_prev = w.bslab;
+    d.bstate = w.bsink;
+    launch_bead_stats(d, -1, s);
+  }
+  hipStream_t S = w.side;
+  hipEvent_t* ev = w.ev;
+  (void)hipEventRecord(ev[8], s);
+  (void)hipStreamWaitEvent(S, ev[8], 0);
+  // Recompute, as lbm_step's concurrent schedule: step i's bead statistics,
+  // forces and spreading (side stream, after advecting step i-1) beside the
+  // bulk stream-collide of step i (main stream); the near-block launch joins
+  // both.  Step i reads the markers of pslab[i], advects them into
+  // pslab[i+1], writes its bead statistics to bslab[i+1] taking the
+  // previous centres (the volume's reference point) from bslab[i], and
+  // marks the near blocks of step i+1 into entry i+1.
+  for (int i = 0; i < m; ++i) {
+    Dev d = dS;
+    d.sub = i;
+    d.pos = w.pslab + i * 3 * nm;
+    d.bstate_prev = w.bslab + i * nb;
+    d.bstate = w.bslab + (i + 1) * nb;
+    d.fm = w.fslab + i * 3 * nm;
+    d.F = w.Fslab + (size_t)i * 3 * ps;
+    d.stamp = w.stslab + (size_t)i * h->ntiles;
+    d.mom = w.mom + (size_t)i * h->nodes;
+    if (i > 0) {
+      (void)hipEventRecord(ev[i & 1], s);  // near-block launch i-1 done
+      (void)hipStreamWaitEvent(S, ev[i & 1], 0);
+      launch_interp_advance(advect_view(dS, w, i - 1, nm), S);
+    }
+    const Dev dm = with_near(d, near_view(dS, w, i + 1));
+    launch_bead_stats(dm, 0, S);
+    launch_vertex_forces(dm, S);
+    launch_spread(dm, S);
+    (void)hipEventRecord(ev[2 + (i & 1)], S);
+    const Dev dr = with_near(d, near_view(dS, w, i));
+    launch_stream_collide_mom(dr, kLaunchBulk, nblocks, s);
+    (void)hipStreamWaitEvent(s, ev[2 + (i & 1)], 0);
+    launch_stream_collide_mom(dr, kLaunchActive, nblocks, s);
+  }
+  (void)hipEventRecord(ev[8], s);
+  (void)hipStreamWaitEvent(S, ev[8], 0);
+  launch_interp_advance(advect_view(dS, w, m - 1, nm), S);
+  (void)hipEventRecord(ev[9], S);
+  (void)hipStreamWaitEvent(s, ev[9], 0);
+  // Reverse steps of the segment, last to first.  The main stream runs the adjoint
+  // collide of the blocks away from the swimmers; the side stream spreads
+  // lambda_u, runs the near blocks, then the marker adjoints.  Bulk i reads
+  // (and its parity is read by) near-block launch i+1; near-block launch i
+  // likewise pairs with bulk i+1.
+  (void)hipEventRecord(ev[8], s);
+  (void)hipStreamWaitEvent(S, ev[8], 0);
+  for (int i = m - 1; i >= 0; --i) {
+    const int n = par + i;  // the parity of the step index is all that is used
+    Dev d = dS;
+    d.sub = i;
+    d.pos = w.pslab + i * 3 * nm;
+    d.bstate = w.bslab + (i + 1) * nb;
+    d.fm = w.fslab + i * 3 * nm;
+    d.F = w.Fslab + (size_t)i * 3 * ps;  // F_n, kept by the recompute
+    d.stamp = w.stslab + (size_t)i * h->ntiles;
+    const Dev dr = with_near(d, near_view(dS, w, i));
+    a.Lsrc = w.L + ((n + 1) & 1) * popn;
+    a.Ldst = w.L + (n & 1) * popn;
+    a.mom = w.mom + (size_t)i * h->nodes;
+    const bool first = i == m - 1;
+    hipEvent_t bulk_now = ev[4 + (i & 1)], bulk_prev = ev[4 + ((i + 1) & 1)];
+    hipEvent_t near_now = ev[6 + (i & 1)], near_prev = ev[6 + ((i + 1) & 1)];
+    if (!first) (void)hipStreamWaitEvent(s, near_prev, 0);
+    launch_adj_collide(dr, a, kLaunchBulk, nblocks, s);
+    (void)hipEventRecord(bulk_now, s);
+    Dev dl = d;
+    dl.fm = w.lr32;
+    dl.F = w.lu;
+    launch_spread(dl, S);  // lambda_u = S(r_n) lambda_r(n+1), same tiles as F_n
+    if (!first) (void)hipStreamWaitEvent(S, bulk_prev, 0);
+    launch_adj_collide(dr, a, kLaunchActive, nblocks, S);
+    (void)hipEventRecord(near_now, S);
+    launch_adj_gather(d, a, S);
+    launch_adj_bead(d, a, S);
+    launch_adj_tangent(d, a, S);
+  }
+  (void)hipEventRecord(ev[9], S);
+  (void)hipStreamWaitEvent(s, ev[9], 0);
+}
+
+// Segments replay captured HIP graphs (one per length and parity) when the
+// handle steps with graphs, else enqueue directly.
+int enqueue_or_replay(lbm_handle* h, AdjWork& w, const Dev& dS, const Adj& a, int m, int par, int nblocks) {
+  if (!h->use_graphs) {
+    enqueue_segment(h, w, dS, a, m, par, nblocks);
+    return h->hip(hipGetLastError(), "adjoint launch");
+  }
+  const int64_t key = 2 * (int64_t)m + par;
+  hipGraphExec_t& g = w.graphs[key];
+  if (!g) {
+    hipGraph_t graph = nullptr;
+    int rc = h->hip(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    if (rc) return rc;
+    enqueue_segment(h, w, dS, a, m, par, nblocks);
+    rc = h->hip(hipStreamEndCapture(h->stream, &graph), "hipStreamEndCapture");
+    if (!rc) rc = h->hip(hipGraphInstantiate(&g, graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+    if (graph) (void)hipGraphDestroy(graph);
+    if (rc) {
+      g = nullptr;
+      return rc;
+    }
+  }
+  return h->hip(hipGraphLaunch(g, h->stream), "hipGraphLaunch");
 }
 
 // Copy on the handle's stream.
@@ -150,10 +333,10 @@ int run(lbm_handle* h, const lbm_adjoint_desc* ad, double* J, double* grad) {
   dS.u = w.u;
   dS.step = w.step;
   dS.U = w.U;
-  dS.near = w.near;
-  dS.near_list = w.near_list;
-  dS.near_count = w.near_count;
   dS.overflow = w.overflow;
+  dS.nsc = w.nsc;
+  dS.sc_bs = kScBlock;
+  dS.max_near = w.max_near;
   Adj a{};
   a.lu = w.lu;
   a.lF = w.lF;
@@ -164,10 +347,10 @@ int run(lbm_handle* h, const lbm_adjoint_desc* ad, double* J, double* grad) {
   a.bsum = w.bsum;
   a.grad = w.grad;
   a.swimmer = ad->swimmer;
-  const size_t nsc_max = (size_t)((h->nodes + 127) / 128);
   rc = h->hip(hipMemsetAsync(w.L, 0, sizeof(float) * 2 * popn, s), "hipMemsetAsync");
   if (!rc) rc = h->hip(hipMemsetAsync(w.stslab, 0x80, sizeof(int) * (size_t)K * h->ntiles, s), "hipMemsetAsync");
-  if (!rc) rc = h->hip(hipMemsetAsync(w.near, 0x80, sizeof(int) * 2 * nsc_max, s), "hipMemsetAsync");
+  if (!rc)
+    rc = h->hip(hipMemsetAsync(w.nflag, 0x80, sizeof(int) * (size_t)(K + 1) * 2 * w.nsc, s), "hipMemsetAsync");
   if (!rc) rc = h->hip(hipMemsetAsync(w.overflow, 0, sizeof(int), s), "hipMemsetAsync");
   if (rc) return rc;
   launch_adj_init(dS, a, s);
@@ -179,52 +362,11 @@ int run(lbm_handle* h, const lbm_adjoint_desc* ad, double* J, double* grad) {
     rc = dcopy(h, w.P + (n0 & 1) * popn, w.ck_pop + c * popn, sizeof(float) * popn);
     if (!rc) rc = dcopy(h, w.pslab, w.ck_pos + c * 3 * nm, sizeof(double) * 3 * nm);
     if (!rc) rc = dcopy(h, w.bslab, w.ck_bst + c * nb, sizeof(BeadState) * nb);
-    if (!rc) rc = h->hip(hipMemsetAsync(w.near_count, 0, sizeof(int) * 2, s), "hipMemsetAsync");
+    if (!rc) rc = h->hip(hipMemsetAsync(w.ncount, 0, sizeof(int) * (size_t)(K + 1) * 2, s), "hipMemsetAsync");
     if (rc) return rc;
     launch_set_step(w.step, n0, s);
-    // recompute: step i reads the markers of pslab[i] and advects them into
-    // pslab[i+1]; its bead statistics go to bslab[i+1], taking the previous
-    // centres (the volume's reference point) from bslab[i]
-    for (int i = 0; i < m; ++i) {
-      Dev d = dS;
-      d.sub = i;
-      d.pos = w.pslab + i * 3 * nm;
-      d.pos_next = w.pslab + (i + 1) * 3 * nm;
-      d.bstate_prev = w.bslab + i * nb;
-      d.bstate = w.bslab + (i + 1) * nb;
-      d.fm = w.fslab + i * 3 * nm;
-      d.F = w.Fslab + (size_t)i * 3 * ps;
-      d.stamp = w.stslab + (size_t)i * h->ntiles;
-      d.mom = w.mom + (size_t)i * h->nodes;
-      launch_bead_stats(d, 0, s);
-      launch_vertex_forces(d, s);
-      launch_spread(d, s);
-      launch_stream_collide_mom(d, nblocks, s);
-      d.sub = i + 1;
-      launch_interp_advance(d, s);
-    }
-    // reverse steps n = n0 + m - 1 ... n0
-    for (int i = m - 1; i >= 0; --i) {
-      const int64_t n = n0 + i;
-      Dev d = dS;
-      d.sub = i;
-      d.pos = w.pslab + i * 3 * nm;
-      d.bstate = w.bslab + (i + 1) * nb;
-      d.fm = w.fslab + i * 3 * nm;
-      d.F = w.Fslab + (size_t)i * 3 * ps;  // F_n, kept by the recompute
-      d.stamp = w.stslab + (size_t)i * h->ntiles;
-      Dev dl = d;
-      dl.fm = w.lr32;
-      dl.F = w.lu;
-      launch_spread(dl, s);  // lambda_u = S(r_n) lambda_r(n+1), same tiles as F_n
-      a.Lsrc = w.L + ((n + 1) & 1) * popn;
-      a.Ldst = w.L + (n & 1) * popn;
-      a.mom = w.mom + (size_t)i * h->nodes;
-      launch_adj_collide(d, a, nblocks, s);
-      launch_adj_gather(d, a, s);
-      launch_adj_bead(d, a, s);
-      launch_adj_tangent(d, a, s);
-    }
+    rc = enqueue_or_replay(h, w, dS, a, m, (int)(n0 & 1), nblocks);
+    if (rc) return rc;
     rc = h->hip(hipGetLastError(), "adjoint launch");
     if (rc) return rc;
   }

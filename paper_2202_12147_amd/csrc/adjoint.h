@@ -30,8 +30,10 @@ struct Adj {
 
 // lambda_r(T) = x^/(3 N_v) on the swimmer's nodes, zero elsewhere; grad = 0.
 void launch_adj_init(const Dev& d, const Adj& a, hipStream_t s);
-// Collision VJP and adjoint (push) streaming at every node.
-void launch_adj_collide(const Dev& d, const Adj& a, int nblocks, hipStream_t s);
+// Collision VJP and adjoint (push) streaming, in the launch modes of the
+// forward stream-collide (kLaunchAll: every node; kLaunchBulk: blocks not
+// marked near for step n; kLaunchActive: the near list), blocks of 256 nodes.
+void launch_adj_collide(const Dev& d, const Adj& a, int mode, int nblocks, hipStream_t s);
 // Transposed spreading and interpolation at the markers.
 void launch_adj_gather(const Dev& d, const Adj& a, hipStream_t s);
 // Per-bead sums of the force adjoint and the volume tangent.

@@ -55,11 +55,21 @@ __device__ inline double3 ld3(const double* p, int nm, int m) { return make_doub
 // at y equal lambda_f,i(y + c_i): each node pulls Lambda_i from y + c_i and
 // stores its own lambda_f (reads shifted by one element, writes coalesced);
 // same block layout as the populations.
-__global__ __launch_bounds__(kBlock) void k_adj_collide(Dev d, Adj a) {
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_adj_collide(Dev d, Adj a, int nblocks) {
   const Box B = d.boxes[0];
-  const int id = blockIdx.x * kBlock + threadIdx.x;
-  if (id >= B.n) return;
   const int64_t n = *d.step + d.sub;
+  const int64_t pn = n - 1;  // the near marks of step n were made at step n - 1
+  const int pp = (int)(pn & 1);
+  int blk = blockIdx.x;
+  if constexpr (MODE == kLaunchActive) {
+    if ((int)blockIdx.x >= min(d.near_count[pp], d.max_near)) return;
+    blk = d.near_list[pp * d.max_near + blockIdx.x];
+  } else if constexpr (MODE == kLaunchBulk) {
+    if (blk >= nblocks || d.near[pp * d.nsc + blk] == (int)pn) return;
+  }
+  const int id = blk * kBlock + threadIdx.x;
+  if (id >= B.n) return;
   const int nx = B.nx, ny = B.ny, nz = B.nz;
   const int x = id % nx, yz = id / nx, y = yz % ny, z = yz / ny;
   const int sz = nx * ny;
@@ -79,7 +89,10 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(Dev d, Adj a) {
   const float rho = mu.x, ux = mu.y, uy = mu.z, uz = mu.w;
   float Fx = B.gx, Fy = B.gy, Fz = B.gz, lux = 0.0f, luy = 0.0f, luz = 0.0f;
   const int tile = B.tile0 + (x / kTile) + B.tx * ((y / kTile) + B.ty * (z / kTile));
-  const bool forced = d.stamp[tile] == (int)n;
+  // bulk blocks are never forced: the nodes of an active tile outside the
+  // near blocks carry F = 0 and lambda_u = 0, and no stencil reads their
+  // lambda_F (the side stream is rewriting lambda_u meanwhile)
+  const bool forced = MODE != kLaunchBulk && d.stamp[tile] == (int)n;
   if (forced) {
     Fx += d.F[base];
     Fy += d.F[ps + base];
@@ -520,8 +533,13 @@ void launch_adj_init(const Dev& d, const Adj& a, hipStream_t s) {
   hipLaunchKernelGGL(k_adj_init, dim3((d.nm + kBlock - 1) / kBlock), dim3(kBlock), 0, s, d, a);
 }
 
-void launch_adj_collide(const Dev& d, const Adj& a, int nblocks, hipStream_t s) {
-  hipLaunchKernelGGL(k_adj_collide, dim3(nblocks), dim3(kBlock), 0, s, d, a);
+void launch_adj_collide(const Dev& d, const Adj& a, int mode, int nblocks, hipStream_t s) {
+  if (mode == kLaunchActive)
+    hipLaunchKernelGGL(k_adj_collide<kLaunchActive>, dim3(d.max_near), dim3(kBlock), 0, s, d, a, nblocks);
+  else if (mode == kLaunchBulk)
+    hipLaunchKernelGGL(k_adj_collide<kLaunchBulk>, dim3(nblocks), dim3(kBlock), 0, s, d, a, nblocks);
+  else
+    hipLaunchKernelGGL(k_adj_collide<kLaunchAll>, dim3(nblocks), dim3(kBlock), 0, s, d, a, nblocks);
 }
 
 void launch_adj_gather(const Dev& d, const Adj& a, hipStream_t s) {

@@ -148,9 +148,10 @@ struct Dev {
 void launch_stream_collide(const Dev& d, int storage, int mode, int block, int nblocks, int remap,
                            int resident, int ncu, hipStream_t s, hipEvent_t ev0 = nullptr,
                            hipEvent_t ev1 = nullptr);
-// Full-grid stream-collide (FP32 storage, single box) that also writes each
-// node's (rho, u_x, u_y, u_z) to d.mom.
-void launch_stream_collide_mom(const Dev& d, int nblocks, hipStream_t s);
+// Stream-collide (FP32 storage, single box, workgroups of kScBlock nodes,
+// launch mode kLaunchAll / kLaunchBulk / kLaunchActive) that also writes each
+// node's (rho, u_x, u_y, u_z) to d.mom; nblocks = node blocks of the box.
+void launch_stream_collide_mom(const Dev& d, int mode, int nblocks, hipStream_t s);
 void launch_tick(const Dev& d, int count, hipStream_t s);
 void launch_velocity(const Dev& d, int storage, int nblocks, float* u_out, float* rho_out,
                      hipStream_t s);

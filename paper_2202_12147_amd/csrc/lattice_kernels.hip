@@ -271,10 +271,22 @@ __global__ __launch_bounds__(BS) void k_stream_collide(Dev d, int remap, int nbl
   }
 }
 
-// Full grid, FP32, recording (rho, u) per node (adjoint segment recompute).
-__global__ __launch_bounds__(kScBlock) void k_stream_collide_mom(Dev d) {
+// FP32, recording (rho, u) per node (adjoint segment recompute), in the
+// three launch modes of k_stream_collide with workgroups of kScBlock nodes.
+template <int MODE>
+__global__ __launch_bounds__(kScBlock) void k_stream_collide_mom(Dev d, int nblocks) {
   const int64_t n = *d.step + d.sub;
-  sc_block<kFp32, kScBlock, true>(d, blockIdx.x, n, false);
+  const int64_t pn = n - 1;
+  const int pp = (int)(pn & 1);
+  if constexpr (MODE == kScActive) {
+    const int cnt = min(d.near_count[pp], d.max_near);
+    if ((int)blockIdx.x < cnt) sc_block<kFp32, kScBlock, true>(d, d.near_list[pp * d.max_near + blockIdx.x], n, false);
+  } else if constexpr (MODE == kScBulk) {
+    const int blk = blockIdx.x;
+    if (blk < nblocks && d.near[pp * d.nsc + blk] != (int)pn) sc_block<kFp32, kScBlock, true>(d, blk, n, true);
+  } else {
+    if ((int)blockIdx.x < nblocks) sc_block<kFp32, kScBlock, true>(d, blockIdx.x, n, false);
+  }
 }
 
 // Advance the step counter past an enqueued chunk of `count` steps.
@@ -457,8 +469,13 @@ void launch_stream_collide(const Dev& d, int storage, int mode, int block, int n
     launch_sc_st<kFp32>(d, mode, block, nblocks, remap, resident, ncu, s, ev0, ev1);
 }
 
-void launch_stream_collide_mom(const Dev& d, int nblocks, hipStream_t s) {
-  hipLaunchKernelGGL(k_stream_collide_mom, dim3(nblocks), dim3(kScBlock), 0, s, d);
+void launch_stream_collide_mom(const Dev& d, int mode, int nblocks, hipStream_t s) {
+  if (mode == kScActive)
+    hipLaunchKernelGGL(k_stream_collide_mom<kScActive>, dim3(d.max_near), dim3(kScBlock), 0, s, d, nblocks);
+  else if (mode == kScBulk)
+    hipLaunchKernelGGL(k_stream_collide_mom<kScBulk>, dim3(nblocks), dim3(kScBlock), 0, s, d, nblocks);
+  else
+    hipLaunchKernelGGL(k_stream_collide_mom<kScAll>, dim3(nblocks), dim3(kScBlock), 0, s, d, nblocks);
 }
 
 void launch_tick(const Dev& d, int count, hipStream_t s) {
