@@ -254,13 +254,17 @@ __global__ __launch_bounds__(BS) void k_stream_collide(Dev d, int remap, int nbl
     const int cnt = min(d.near_count[pp], d.max_near);
     if ((int)blockIdx.x < cnt) sc_block<ST, BS>(d, d.near_list[pp * d.max_near + blockIdx.x], n, false);
   } else if constexpr (MODE == kScBulk) {
-    if (resident) {
+    if (resident && remap) {
       const int per = (nblocks + 7) / 8;  // logical blocks per XCD
       const int xcd = blockIdx.x % 8, g8 = (int)gridDim.x / 8;
       for (int j = blockIdx.x / 8; j < per; j += g8) {
         const int blk = xcd * per + j;
         if (blk < nblocks && d.near[pp * d.nsc + blk] != (int)pn) sc_block<ST, BS>(d, blk, n, true);
       }
+    } else if (resident) {
+      // grid-stride: consecutive blocks go to consecutive workgroups (round robin over the XCDs)
+      for (int blk = blockIdx.x; blk < nblocks; blk += (int)gridDim.x)
+        if (d.near[pp * d.nsc + blk] != (int)pn) sc_block<ST, BS>(d, blk, n, true);
     } else {
       const int blk = logical_block(remap, nblocks);
       if (blk < nblocks && d.near[pp * d.nsc + blk] != (int)pn) sc_block<ST, BS>(d, blk, n, true);
@@ -438,7 +442,8 @@ static void launch_sc_mode(const Dev& d, int block, int nblocks, int remap, int 
                            hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   int grid = remap ? (nblocks + 7) / 8 * 8 : nblocks;
   if (MODE == kScActive) grid = d.max_near;
-  if (MODE == kScBulk && resident > 0) grid = std::min(grid, ncu * resident) / 8 * 8;
+  if (MODE == kScBulk && resident > 0)
+    grid = remap ? std::min(grid, ncu * resident) / 8 * 8 : std::min(grid, ncu * resident);
   if (MODE != kScBulk) resident = 0;
   if (block == 128)
     launch_k(k_stream_collide<ST, 128, MODE>, grid, 128, s, ev0, ev1, d, remap, nblocks, resident);

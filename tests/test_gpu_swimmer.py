@@ -114,7 +114,7 @@ def test_swimmer_add_after_step_rejected():
     assert e.value.code == -4
 
 
-@pytest.mark.parametrize("block,remap,resident", [(128, 0, 0), (256, 1, 2), (512, 1, 1)])
+@pytest.mark.parametrize("block,remap,resident", [(128, 0, 0), (256, 1, 2), (512, 1, 1), (256, 0, 2), (512, 0, 3)])
 def test_launch_shapes_bitwise_equal_with_swimmer(block, remap, resident):
     # the concurrent bulk / active split and its launch shape must not change
     # a single bit of the result
