@@ -4,8 +4,8 @@
 // The forward run is plain stepping (lbm_step) with the populations, markers
 // and bead statistics copied aside every K steps.  Segments are then taken in
 // reverse order: the segment's forward steps are recomputed from its
-// checkpoint on scratch buffers (the serial kernel order of lbm_step, so the
-// trajectory is bitwise the forward one), keeping per step the markers, the
+// checkpoint on scratch buffers (lbm_step's concurrent bulk / near-block
+// schedule, so the trajectory is bitwise the forward one), keeping per step the markers, the
 // bead statistics, the marker forces, the force density with its tile stamps
 // and (rho, u) of every node; then its reverse steps run from last to first.
 // The handle's own state is only touched by the forward run.
