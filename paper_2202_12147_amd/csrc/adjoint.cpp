@@ -45,7 +45,7 @@ struct AdjWork {
   int64_t* step = nullptr;
   int* overflow = nullptr;
   // near-block marks of every segment step (blocks of kScBlock nodes): flags
-  // [K+1][2][nsc], lists [K+1][2][max_near], counts [K+1][2]; entry i holds
+  // [K+1][kNearSlots][nsc], lists [K+1][2][max_near], counts [K+1][2]; entry i holds
   // the marks step i's launches read (made by step i-1's bead statistics)
   int nsc = 0, max_near = 0;
   int *nflag = nullptr, *nlist = nullptr, *ncount = nullptr, *count_sink = nullptr;
@@ -116,7 +116,7 @@ int ensure_work(lbm_handle* h, int64_t nck, int K) {
     mx += sy * sz * (sx / kScBlock + 2);
   }
   w->max_near = (int)std::max<int64_t>(1, std::min<int64_t>(mx, w->nsc));
-  w->nflag = w->alloc<int>((size_t)(K + 1) * 2 * w->nsc, rc);
+  w->nflag = w->alloc<int>((size_t)(K + 1) * kNearSlots * w->nsc, rc);
   w->nlist = w->alloc<int>((size_t)(K + 1) * 2 * w->max_near, rc);
   w->ncount = w->alloc<int>((size_t)(K + 1) * 2, rc);
   w->count_sink = w->alloc<int>(2, rc);
@@ -143,7 +143,7 @@ int ensure_work(lbm_handle* h, int64_t nck, int K) {
 // marks of segment step i.
 Dev near_view(const Dev& base, const AdjWork& w, int i) {
   Dev d = base;
-  d.near = w.nflag + (size_t)i * 2 * w.nsc;
+  d.near = w.nflag + (size_t)i * kNearSlots * w.nsc;
   d.near_list = w.nlist + (size_t)i * 2 * w.max_near;
   d.near_count = w.ncount + (size_t)i * 2;
   return d;
@@ -350,7 +350,7 @@ int run(lbm_handle* h, const lbm_adjoint_desc* ad, double* J, double* grad) {
   rc = h->hip(hipMemsetAsync(w.L, 0, sizeof(float) * 2 * popn, s), "hipMemsetAsync");
   if (!rc) rc = h->hip(hipMemsetAsync(w.stslab, 0x80, sizeof(int) * (size_t)K * h->ntiles, s), "hipMemsetAsync");
   if (!rc)
-    rc = h->hip(hipMemsetAsync(w.nflag, 0x80, sizeof(int) * (size_t)(K + 1) * 2 * w.nsc, s), "hipMemsetAsync");
+    rc = h->hip(hipMemsetAsync(w.nflag, 0x80, sizeof(int) * (size_t)(K + 1) * kNearSlots * w.nsc, s), "hipMemsetAsync");
   if (!rc) rc = h->hip(hipMemsetAsync(w.overflow, 0, sizeof(int), s), "hipMemsetAsync");
   if (rc) return rc;
   launch_adj_init(dS, a, s);

@@ -60,13 +60,13 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(Dev d, Adj a, int nblock
   const Box B = d.boxes[0];
   const int64_t n = *d.step + d.sub;
   const int64_t pn = n - 1;  // the near marks of step n were made at step n - 1
-  const int pp = (int)(pn & 1);
+  const int pp = (int)(pn & 1), pf = near_slot(pn);
   int blk = blockIdx.x;
   if constexpr (MODE == kLaunchActive) {
     if ((int)blockIdx.x >= min(d.near_count[pp], d.max_near)) return;
     blk = d.near_list[pp * d.max_near + blockIdx.x];
   } else if constexpr (MODE == kLaunchBulk) {
-    if (blk >= nblocks || d.near[pp * d.nsc + blk] == (int)pn) return;
+    if (blk >= nblocks || d.near[pf * d.nsc + blk] == (int)pn) return;
   }
   const int id = blk * kBlock + threadIdx.x;
   if (id >= B.n) return;

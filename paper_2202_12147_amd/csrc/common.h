@@ -22,6 +22,16 @@ namespace lbmib {
 constexpr int kQ = 19;
 constexpr int kTile = 8;       // active-tile edge in nodes
 constexpr int kScBlock = 256;  // stream-collide threads per block
+// Near-block flags hold three step slots (step mod 3): the bead statistics of
+// step n mark slot n mod 3 while the bulk launch of step n - 1, which may
+// still be running, reads slot (n - 2) mod 3.  Lists and counts, read only by
+// the near-block launch that precedes the next marking on the same stream,
+// keep two (step parity).
+constexpr int kNearSlots = 3;
+__host__ __device__ inline int near_slot(int64_t v) {
+  const int r = (int)(v % kNearSlots);
+  return r < 0 ? r + kNearSlots : r;
+}
 constexpr int kPopBlock = 256; // nodes per population block (a power of two: shifts and masks)
 
 // Element index of population q of global node `node`.  A wavefront's 64

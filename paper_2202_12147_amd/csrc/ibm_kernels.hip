@@ -105,7 +105,7 @@ __device__ inline double block_sum(double v, double* sh) {
 // axis, periodic) as near at step v, listing each newly marked block once.
 __device__ inline void mark_near_blocks(const Dev& d, const Box& B, int box, const int* lo, const int* hi,
                                         int64_t v) {
-  const int p = (int)(v & 1);
+  const int p = (int)(v & 1), pf = near_slot(v);
   const int first = d.nboxes == 1 ? 0 : d.sc_box_block0[box];
   const int x0 = lo[0] - 2, nxs = hi[0] - lo[0] + 5;
   const int ny_r = min(hi[1] - lo[1] + 5, B.ny), nz_r = min(hi[2] - lo[2] + 5, B.nz);
@@ -122,7 +122,7 @@ __device__ inline void mark_near_blocks(const Dev& d, const Box& B, int box, con
     for (int sgi = 0; sgi < 2; ++sgi) {
       if (seg[sgi][1] < seg[sgi][0]) continue;
       for (int blk = first + (row + seg[sgi][0]) / d.sc_bs; blk <= first + (row + seg[sgi][1]) / d.sc_bs; ++blk) {
-        if (atomicExch(&d.near[p * d.nsc + blk], (int)v) != (int)v) {
+        if (atomicExch(&d.near[pf * d.nsc + blk], (int)v) != (int)v) {
           const int i = atomicAdd(&d.near_count[p], 1);
           if (i < d.max_near)
             d.near_list[p * d.max_near + i] = blk;

@@ -249,7 +249,7 @@ template <int ST, int BS, int MODE>
 __global__ __launch_bounds__(BS) void k_stream_collide(Dev d, int remap, int nblocks, int resident) {
   const int64_t n = *d.step + d.sub;
   const int64_t pn = n - 1;  // the step whose bead statistics marked the near blocks
-  const int pp = (int)(pn & 1);
+  const int pp = (int)(pn & 1), pf = near_slot(pn);
   if constexpr (MODE == kScActive) {
     const int cnt = min(d.near_count[pp], d.max_near);
     if ((int)blockIdx.x < cnt) sc_block<ST, BS>(d, d.near_list[pp * d.max_near + blockIdx.x], n, false);
@@ -259,15 +259,15 @@ __global__ __launch_bounds__(BS) void k_stream_collide(Dev d, int remap, int nbl
       const int xcd = blockIdx.x % 8, g8 = (int)gridDim.x / 8;
       for (int j = blockIdx.x / 8; j < per; j += g8) {
         const int blk = xcd * per + j;
-        if (blk < nblocks && d.near[pp * d.nsc + blk] != (int)pn) sc_block<ST, BS>(d, blk, n, true);
+        if (blk < nblocks && d.near[pf * d.nsc + blk] != (int)pn) sc_block<ST, BS>(d, blk, n, true);
       }
     } else if (resident) {
       // grid-stride: consecutive blocks go to consecutive workgroups (round robin over the XCDs)
       for (int blk = blockIdx.x; blk < nblocks; blk += (int)gridDim.x)
-        if (d.near[pp * d.nsc + blk] != (int)pn) sc_block<ST, BS>(d, blk, n, true);
+        if (d.near[pf * d.nsc + blk] != (int)pn) sc_block<ST, BS>(d, blk, n, true);
     } else {
       const int blk = logical_block(remap, nblocks);
-      if (blk < nblocks && d.near[pp * d.nsc + blk] != (int)pn) sc_block<ST, BS>(d, blk, n, true);
+      if (blk < nblocks && d.near[pf * d.nsc + blk] != (int)pn) sc_block<ST, BS>(d, blk, n, true);
     }
   } else {
     const int blk = logical_block(remap, nblocks);
@@ -281,13 +281,13 @@ template <int MODE>
 __global__ __launch_bounds__(kScBlock) void k_stream_collide_mom(Dev d, int nblocks) {
   const int64_t n = *d.step + d.sub;
   const int64_t pn = n - 1;
-  const int pp = (int)(pn & 1);
+  const int pp = (int)(pn & 1), pf = near_slot(pn);
   if constexpr (MODE == kScActive) {
     const int cnt = min(d.near_count[pp], d.max_near);
     if ((int)blockIdx.x < cnt) sc_block<kFp32, kScBlock, true>(d, d.near_list[pp * d.max_near + blockIdx.x], n, false);
   } else if constexpr (MODE == kScBulk) {
     const int blk = blockIdx.x;
-    if (blk < nblocks && d.near[pp * d.nsc + blk] != (int)pn) sc_block<kFp32, kScBlock, true>(d, blk, n, true);
+    if (blk < nblocks && d.near[pf * d.nsc + blk] != (int)pn) sc_block<kFp32, kScBlock, true>(d, blk, n, true);
   } else {
     if ((int)blockIdx.x < nblocks) sc_block<kFp32, kScBlock, true>(d, blockIdx.x, n, false);
   }

@@ -284,7 +284,7 @@ int upload(lbm_handle* h) {
   h->d_centres = h->alloc<double>(3 * h->beads.size(), rc);
   // near-block buffers, sized for the smallest stream-collide block (128)
   const int64_t nsc_max = (h->nodes + 127) / 128;
-  h->d_near = h->alloc<int>(2 * (size_t)nsc_max, rc);
+  h->d_near = h->alloc<int>(kNearSlots * (size_t)nsc_max, rc);
   h->d_near_list = h->alloc<int>(2 * (size_t)nsc_max, rc);
   h->d_near_count = h->alloc<int>(2, rc);
   if (rc != LBM_OK) return h->fail(rc, "device allocation for markers failed");
@@ -361,7 +361,7 @@ int upload(lbm_handle* h) {
   if (!h->swimmers.empty()) {
     rc = h->hip(hipStreamCreate(&h->side), "hipStreamCreate");
     if (rc) return rc;
-    h->fork_join.resize(2 * kGraphChunk);
+    h->fork_join.resize(2 * kGraphChunk + 1);
     for (auto& e : h->fork_join) {
       rc = h->hip(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreateWithFlags");
       if (rc) return rc;
@@ -388,12 +388,12 @@ void timing_pair(lbm_handle* h, hipEvent_t* e0, hipEvent_t* e1) {
 }
 
 // Enqueue `count` steps.  Without swimmers each step is one full-grid
-// stream-collide launch.  With swimmers, step k forks the IBM chain onto the
-// side stream -- advection of the previous step, bead statistics, nodal
-// forces, spreading -- while the main stream streams and collides every node
-// away from the swimmers; the active-tile launch then joins both and advances
-// the step counter.  The last step's advection closes the sequence, so the
-// markers are current whenever the sequence ends.
+// stream-collide launch.  With swimmers the side stream runs the IBM chain of
+// each step -- advection of the previous step, bead statistics, nodal forces,
+// spreading -- and then the near-block launch, while the main stream streams
+// and collides every node away from the swimmers.  The last step's advection
+// closes the sequence on the main stream after a join, so the markers are
+// current whenever the sequence ends; one kernel advances the step counter.
 void enqueue_steps(lbm_handle* h, int64_t count) {
   Dev d = h->dev;
   if (h->swimmers.empty()) {
@@ -424,24 +424,36 @@ void enqueue_steps(lbm_handle* h, int64_t count) {
     launch_tick(d, (int)count, h->stream);
     return;
   }
+  // The near-block launch of step n needs the spreading of step n and the
+  // populations of step n - 1 (bulk and near blocks), not the bulk launch of
+  // step n; the bulk launch of step n needs the near blocks of step n - 1.
+  // Each stream waits on the other with a lag of one step, so in the steady
+  // state the bulk launches run back to back.
+  hipEvent_t fork = h->fork_join[2 * kGraphChunk];
+  (void)hipEventRecord(fork, h->stream);
+  (void)hipStreamWaitEvent(h->side, fork, 0);
+  hipEvent_t prev_bulk = nullptr, prev_near = nullptr;
   for (int64_t i = 0; i < count; ++i) {
-    hipEvent_t fork = h->fork_join[2 * (i % kGraphChunk)], join = h->fork_join[2 * (i % kGraphChunk) + 1];
-    (void)hipEventRecord(fork, h->stream);
-    (void)hipStreamWaitEvent(h->side, fork, 0);
+    hipEvent_t ev_bulk = h->fork_join[2 * (i % kGraphChunk)], ev_near = h->fork_join[2 * (i % kGraphChunk) + 1];
     d.sub = (int)i;
     if (i > 0) launch_interp_advance(d, h->side);
     launch_bead_stats(d, 0, h->side);
     launch_vertex_forces(d, h->side);
     launch_spread(d, h->side);
-    (void)hipEventRecord(join, h->side);
+    if (prev_near) (void)hipStreamWaitEvent(h->stream, prev_near, 0);
     hipEvent_t e0, e1;
     timing_pair(h, &e0, &e1);
     launch_stream_collide(d, h->storage, kLaunchBulk, h->sc_block, h->sc_blocks, h->sc_remap, h->sc_resident,
                           h->ncu, h->stream, e0, e1);
-    (void)hipStreamWaitEvent(h->stream, join, 0);
+    (void)hipEventRecord(ev_bulk, h->stream);
+    if (prev_bulk) (void)hipStreamWaitEvent(h->side, prev_bulk, 0);
     timing_pair(h, &e0, &e1);
-    launch_stream_collide(d, h->storage, kLaunchActive, h->sc_block, h->sc_blocks, 0, 0, h->ncu, h->stream, e0, e1);
+    launch_stream_collide(d, h->storage, kLaunchActive, h->sc_block, h->sc_blocks, 0, 0, h->ncu, h->side, e0, e1);
+    (void)hipEventRecord(ev_near, h->side);
+    prev_bulk = ev_bulk;
+    prev_near = ev_near;
   }
+  (void)hipStreamWaitEvent(h->stream, prev_near ? prev_near : fork, 0);
   d.sub = (int)count;
   launch_interp_advance(d, h->stream);
   launch_tick(d, (int)count, h->stream);
@@ -452,7 +464,7 @@ void enqueue_steps(lbm_handle* h, int64_t count) {
 // grid into bulk and active parts.  Eager, never captured.
 int prologue(lbm_handle* h) {
   if (!h->need_prologue || h->swimmers.empty()) return LBM_OK;
-  int rc = h->hip(hipMemsetAsync(h->d_near, 0x80, sizeof(int) * 2 * h->dev.nsc, h->stream), "hipMemsetAsync");
+  int rc = h->hip(hipMemsetAsync(h->d_near, 0x80, sizeof(int) * kNearSlots * h->dev.nsc, h->stream), "hipMemsetAsync");
   if (!rc) rc = h->hip(hipMemsetAsync(h->d_near_count, 0, sizeof(int) * 2, h->stream), "hipMemsetAsync");
   if (rc) return rc;
   launch_bead_stats(h->dev, -1, h->stream);
@@ -1061,7 +1073,7 @@ int checkpoint(lbm_handle* h, const char* path, bool save) {
   if (rc) return rc;
   FILE* f = fopen(path, save ? "wb" : "rb");
   if (!f) return h->fail(LBM_EIO, std::string("cannot open ") + path);
-  CkptHeader hd{kMagic, 3, (int32_t)h->boxes.size(), h->storage, h->width, h->nm, (int32_t)h->beads.size(),
+  CkptHeader hd{kMagic, 4, (int32_t)h->boxes.size(), h->storage, h->width, h->nm, (int32_t)h->beads.size(),
                 0, signature(h), h->nodes, h->host_step};
   if (save) {
     if (fwrite(&hd, sizeof hd, 1, f) != 1) rc = h->fail(LBM_EIO, "short write");
@@ -1185,7 +1197,7 @@ void snapshot_parts(lbm_handle* h, Snapshot& S) {
     S.parts.push_back({h->d_U, sizeof(float) * 3 * h->nm});
     S.parts.push_back({h->d_fm, sizeof(float) * 3 * h->nm});
     S.parts.push_back({h->d_bstate, sizeof(BeadState) * h->beads.size()});
-    S.parts.push_back({h->d_near, sizeof(int) * 2 * nsc_max});
+    S.parts.push_back({h->d_near, sizeof(int) * kNearSlots * nsc_max});
     S.parts.push_back({h->d_near_list, sizeof(int) * 2 * nsc_max});
     S.parts.push_back({h->d_near_count, sizeof(int) * 2});
   }
