@@ -115,6 +115,9 @@ struct Dev {
   const Swimmer* swimmers;
   int nswimmers;
   const int* marker_bead;
+  // per marker: bead, box, swimmer * 4 + slot, first bead of the swimmer (one
+  // 16-byte load gives a marker-level kernel every index it dereferences)
+  const int4* marker_info;
   // triangles: vertex ids and reference metric (FP64) / inverse (FP32)
   const int* tri;        // [3][ntri]
   const double* G0;      // [3][ntri]: G11, G12, G22

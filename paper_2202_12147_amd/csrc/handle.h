@@ -55,6 +55,7 @@ struct lbm_handle {
   std::vector<Swimmer> swimmers;
   std::vector<double> pos0;  // [nm][3] initial marker positions
   std::vector<int> marker_bead;
+  std::vector<int> marker_info;  // [nm][4], see Dev::marker_info
   std::vector<int> tri;      // [ntri][3] global vertex ids
   std::vector<double> G0;    // [ntri][3]
   std::vector<double> hingeth0;
@@ -83,6 +84,7 @@ struct lbm_handle {
   BeadState* d_bstate = nullptr;
   Swimmer* d_swimmers = nullptr;
   int *d_marker_bead = nullptr, *d_tri = nullptr, *d_hinge = nullptr;
+  int4* d_marker_info = nullptr;
   double *d_G0 = nullptr, *d_theta0 = nullptr;
   float *d_G0inv = nullptr, *d_A0 = nullptr, *d_idet = nullptr;
   int *d_lane_elem = nullptr, *d_lane_v = nullptr;

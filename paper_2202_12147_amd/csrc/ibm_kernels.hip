@@ -328,18 +328,18 @@ __device__ inline float3 bending_role(const Dev& d, const Bead& Bd, int h, int r
 // f1 = A sin(w n + phi0) x, f3 = B sin(w n + phi0 + alpha) x, f2 = -f1 - f3,
 // springs f_o = -k (|R_o - R_2| - L) (R_o - R_2)/|R_o - R_2| on the outer
 // beads with the opposite force on the middle one.
-__device__ inline void bead_force(const Dev& d, const Swimmer& S, int slot, int64_t n, double* f) {
+__device__ inline void bead_force(const Swimmer& S, int slot, int64_t n, const double* const* c, double* f) {
   const double t = (double)n;
   const double f1 = S.A * sin(S.omega * t + S.phi0);
   const double f3 = S.B * sin(S.omega * t + S.phi0 + S.alpha);
   f[0] = slot == 0 ? f1 : (slot == 2 ? f3 : -f1 - f3);
   f[1] = 0;
   f[2] = 0;
-  const double* R2 = d.bstate[S.bead[1]].c;
+  const double* R2 = c[1];
   for (int sp = 0; sp < 2; ++sp) {
     const int outer = sp == 0 ? 0 : 2;
     if (slot != outer && slot != 1) continue;
-    const double* Ro = d.bstate[S.bead[outer]].c;
+    const double* Ro = c[outer];
     const double dx = Ro[0] - R2[0], dy = Ro[1] - R2[1], dz = Ro[2] - R2[2];
     const double len = sqrt(dx * dx + dy * dy + dz * dz);
     const double s = (slot == outer ? -1.0 : 1.0) * S.k[sp] * (len - S.L0[sp]) / len;
@@ -359,16 +359,27 @@ __global__ __launch_bounds__(256) void k_vertex_forces(Dev d) {
   const int gid = blockIdx.x * 256 + threadIdx.x;
   const int m = gid / kVertLanes, lane = gid % kVertLanes;
   float fx = 0, fy = 0, fz = 0;
-  int b = 0;
+  double fb[3] = {0, 0, 0};
+  int nv = 1;
   if (m < d.nm) {
-    b = d.marker_bead[m];
+    // every load below depends only on this first round of per-marker and
+    // per-lane tables, so the kernel makes two dependent trips to memory
+    const int4 mi = d.marker_info[m];
     const int e = d.lane_elem[gid];
     const int4 v = d.lane_v[gid];
+    const Bead Bd = d.beads[mi.x];
+    nv = Bd.nv;
+    if (lane == 0) {
+      // the bead's driving and spring force from its swimmer's three centres
+      // (the beads of a swimmer are numbered consecutively from mi.w)
+      const BeadState* st = d.bstate + mi.w;
+      const double* c[3] = {st[0].c, st[1].c, st[2].c};
+      bead_force(d.swimmers[mi.z >> 2], mi.z & 3, *d.step + d.sub, c, fb);
+    }
     if (e >= 0) {
-      const Bead Bd = d.beads[b];
       float3 f;
       if (lane < kVertTriLanes) {
-        const BeadState& st = d.bstate[b];
+        const BeadState& st = d.bstate[mi.x];
         const float pv = (float)(Bd.kv * (st.V - Bd.V0) / (6.0 * Bd.V0));
         f = triangle_corner(d, Bd, e / 3, e % 3, v.x, v.y, v.z, st.c, pv);
       } else {
@@ -386,10 +397,7 @@ __global__ __launch_bounds__(256) void k_vertex_forces(Dev d) {
     fz += __shfl_xor(fz, s, 64);
   }
   if (m < d.nm && lane == 0) {
-    const Bead Bd = d.beads[b];
-    double fb[3];
-    bead_force(d, d.swimmers[Bd.swimmer], Bd.slot, *d.step + d.sub, fb);
-    const float inv = 1.0f / (float)Bd.nv;
+    const float inv = 1.0f / (float)nv;
     d.fm[m] = fx + (float)fb[0] * inv;
     d.fm[d.nm + m] = fy + (float)fb[1] * inv;
     d.fm[2 * d.nm + m] = fz + (float)fb[2] * inv;
@@ -558,7 +566,11 @@ __global__ __launch_bounds__(kInterpBlock) void k_interp_advance(Dev d) {
   if (m < d.nm && lane < NW * NW * NW) {
     const int a = lane % NW, bb = (lane / NW) % NW, c = lane / (NW * NW);
     const double3 p = load_pos(d.pos, d.nm, m);
-    const Box B = d.boxes[d.beads[d.marker_bead[m]].box];
+    Box B;
+    if (d.nboxes == 1)
+      B = d.boxes[0];
+    else
+      B = d.boxes[d.marker_info[m].y];
     const int bx = stencil_base<NW>(p.x) + a, by = stencil_base<NW>(p.y) + bb, bz = stencil_base<NW>(p.z) + c;
     const float w = phi<NW>((float)((double)bx - p.x)) * phi<NW>((float)((double)by - p.y)) *
                     phi<NW>((float)((double)bz - p.z));

@@ -271,6 +271,7 @@ int upload(lbm_handle* h) {
   h->d_bstate = h->alloc<BeadState>(h->beads.size(), rc);
   h->d_swimmers = h->alloc<Swimmer>(h->swimmers.size(), rc);
   h->d_marker_bead = h->alloc<int>(nm, rc);
+  h->d_marker_info = h->alloc<int4>(nm, rc);
   h->d_tri = h->alloc<int>(tri.size(), rc);
   h->d_G0 = h->alloc<double>(G0.size(), rc);
   h->d_G0inv = h->alloc<float>(Gi.size(), rc);
@@ -310,6 +311,7 @@ int upload(lbm_handle* h) {
   }
   put(h->d_swimmers, h->swimmers.data(), sizeof(Swimmer) * h->swimmers.size());
   put(h->d_marker_bead, h->marker_bead.data(), sizeof(int) * nm);
+  put(h->d_marker_info, h->marker_info.data(), sizeof(int4) * nm);
   put(h->d_tri, tri.data(), sizeof(int) * tri.size());
   put(h->d_G0, G0.data(), sizeof(double) * G0.size());
   put(h->d_G0inv, Gi.data(), sizeof(float) * Gi.size());
@@ -340,6 +342,7 @@ int upload(lbm_handle* h) {
   d.swimmers = h->d_swimmers;
   d.nswimmers = (int)h->swimmers.size();
   d.marker_bead = h->d_marker_bead;
+  d.marker_info = h->d_marker_info;
   d.tri = h->d_tri;
   d.G0 = h->d_G0;
   d.G0inv = h->d_G0inv;
@@ -798,6 +801,11 @@ int lbm_batch_swimmer_add(lbm_handle* h, int32_t box, const lbm_bead_desc beads[
       }
     h->pos0.insert(h->pos0.end(), x.begin(), x.end());
     h->marker_bead.insert(h->marker_bead.end(), nv, (int)h->beads.size());
+    for (int j = 0; j < nv; ++j) {
+      const int info[4] = {(int)h->beads.size(), b.box, (int)h->swimmers.size() * 4 + k,
+                           (int)h->beads.size() - k};
+      h->marker_info.insert(h->marker_info.end(), info, info + 4);
+    }
     S.bead[k] = (int)h->beads.size();
     h->beads.push_back(b);
     h->nm += nv;
