@@ -142,6 +142,7 @@ __global__ __launch_bounds__(BS) void k_bead_stats(Dev d, int mark_offset) {
   __shared__ int reg_lo[3], reg_hi[3];
   const int b = blockIdx.x;
   const Bead Bd = d.beads[b];
+  const Box Bx = d.boxes[Bd.box];
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
   // The enclosed volume 1/6 sum (r0-c).((r1-c) x (r2-c)) of a closed outward
   // surface does not depend on the reference point c; the previous step's
@@ -184,22 +185,30 @@ __global__ __launch_bounds__(BS) void k_bead_stats(Dev d, int mark_offset) {
   if (lane == 0)
     for (int k = 0; k < NV; ++k) part[wave][k] = v[k];
   __syncthreads();
-  if (threadIdx.x == 0) {
+  // each of the first NV threads folds one statistic over the wavefront
+  // partials (independent LDS reads, issued back to back)
+  if (threadIdx.x < NV) {
+    const int k = threadIdx.x;
+    double t = part[0][k];
     for (int w = 1; w < NWAVE; ++w) {
-      for (int k = 0; k < 3; ++k) part[0][k] += part[w][k];
-      for (int k = 3; k < 6; ++k) part[0][k] = fmin(part[0][k], part[w][k]);
-      for (int k = 6; k < 9; ++k) part[0][k] = fmax(part[0][k], part[w][k]);
-      part[0][9] += part[w][9];
+      const double x = part[w][k];
+      t = (k < 3 || k == 9) ? t + x : (k < 6 ? fmin(t, x) : fmax(t, x));
     }
+    part[0][k] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) t[k] = part[0][k];
     BeadState& st = d.bstate[b];
-    const Box B = d.boxes[Bd.box];
-    const int T[3] = {B.tx, B.ty, B.tz};
+    const int T[3] = {Bx.tx, Bx.ty, Bx.tz};
     const int reserved[3] = {Bd.tiles_x, Bd.tiles_y, Bd.tiles_z};
-    for (int a = 0; a < 3; ++a) st.c[a] = part[0][a] / Bd.nv;
-    st.V = part[0][9] / 6.0;
+    for (int a = 0; a < 3; ++a) st.c[a] = t[a] / Bd.nv;
+    st.V = t[9] / 6.0;
     for (int a = 0; a < 3; ++a) {
-      st.lo[a] = stencil_base<NW>(part[0][3 + a]);
-      st.hi[a] = stencil_base<NW>(part[0][6 + a]) + NW - 1;
+      st.lo[a] = stencil_base<NW>(t[3 + a]);
+      st.hi[a] = stencil_base<NW>(t[6 + a]) + NW - 1;
       int t0 = floor_div(st.lo[a], kTile);
       int cnt = floor_div(st.hi[a], kTile) - t0 + 1;
       if (cnt >= T[a]) {
@@ -219,7 +228,7 @@ __global__ __launch_bounds__(BS) void k_bead_stats(Dev d, int mark_offset) {
   }
   __syncthreads();
   // blocks the next step's stream-collide must treat as near this bead
-  mark_near_blocks(d, d.boxes[Bd.box], Bd.box, reg_lo, reg_hi, *d.step + d.sub + mark_offset);
+  mark_near_blocks(d, Bx, Bd.box, reg_lo, reg_hi, *d.step + d.sub + mark_offset);
 }
 
 // ---- membrane forces ------------------------------------------------------------
