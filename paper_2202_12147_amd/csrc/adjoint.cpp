@@ -188,13 +188,14 @@ void enqueue_segment(lbm_handle* h, AdjWork& w, const Dev& dS, Adj a, int m, int
   hipEvent_t* ev = w.ev;
   (void)hipEventRecord(ev[8], s);
   (void)hipStreamWaitEvent(S, ev[8], 0);
-  // Recompute, as lbm_step's concurrent schedule: step i's bead statistics,
-  // forces and spreading (side stream, after advecting step i-1) beside the
-  // bulk stream-collide of step i (main stream); the near-block launch joins
-  // both.  Step i reads the markers of pslab[i], advects them into
-  // pslab[i+1], writes its bead statistics to bslab[i+1] taking the
-  // previous centres (the volume's reference point) from bslab[i], and
-  // marks the near blocks of step i+1 into entry i+1.
+  // Recompute, as lbm_step's concurrent schedule: the side stream advects
+  // step i-1, then runs step i's bead statistics, forces, spreading and
+  // near-block launch (after the bulk launch of step i-1); the main stream
+  // runs the bulk launch of step i (after the near-block launch of step i-1).
+  // Step i reads the markers of pslab[i], advects them into pslab[i+1],
+  // writes its bead statistics to bslab[i+1] taking the previous centres
+  // (the volume's reference point) from bslab[i], and marks the near blocks
+  // of step i+1 into entry i+1.
   for (int i = 0; i < m; ++i) {
     Dev d = dS;
     d.sub = i;
@@ -205,20 +206,20 @@ void enqueue_segment(lbm_handle* h, AdjWork& w, const Dev& dS, Adj a, int m, int
     d.F = w.Fslab + (size_t)i * 3 * ps;
     d.stamp = w.stslab + (size_t)i * h->ntiles;
     d.mom = w.mom + (size_t)i * h->nodes;
-    if (i > 0) {
-      (void)hipEventRecord(ev[i & 1], s);  // near-block launch i-1 done
-      (void)hipStreamWaitEvent(S, ev[i & 1], 0);
-      launch_interp_advance(advect_view(dS, w, i - 1, nm), S);
-    }
+    hipEvent_t bulk_now = ev[i & 1], bulk_prev = ev[(i + 1) & 1];
+    hipEvent_t near_now = ev[2 + (i & 1)], near_prev = ev[2 + ((i + 1) & 1)];
+    if (i > 0) launch_interp_advance(advect_view(dS, w, i - 1, nm), S);
     const Dev dm = with_near(d, near_view(dS, w, i + 1));
     launch_bead_stats(dm, 0, S);
     launch_vertex_forces(dm, S);
     launch_spread(dm, S);
-    (void)hipEventRecord(ev[2 + (i & 1)], S);
     const Dev dr = with_near(d, near_view(dS, w, i));
+    if (i > 0) (void)hipStreamWaitEvent(s, near_prev, 0);
     launch_stream_collide_mom(dr, kLaunchBulk, nblocks, s);
-    (void)hipStreamWaitEvent(s, ev[2 + (i & 1)], 0);
-    launch_stream_collide_mom(dr, kLaunchActive, nblocks, s);
+    (void)hipEventRecord(bulk_now, s);
+    if (i > 0) (void)hipStreamWaitEvent(S, bulk_prev, 0);
+    launch_stream_collide_mom(dr, kLaunchActive, nblocks, S);
+    (void)hipEventRecord(near_now, S);
   }
   (void)hipEventRecord(ev[8], s);
   (void)hipStreamWaitEvent(S, ev[8], 0);
