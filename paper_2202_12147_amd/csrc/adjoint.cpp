@@ -8,6 +8,9 @@
 // schedule, so the trajectory is bitwise the forward one), keeping per step the markers, the
 // bead statistics, the marker forces, the force density with its tile stamps
 // and (rho, u) of every node; then its reverse steps run from last to first.
+// Segment storage is double-buffered: the recompute of segment c - 1 runs on
+// its own pair of streams while the reverse sweep of segment c runs on the
+// handle's stream and the adjoint side stream.
 // The handle's own state is only touched by the forward run.
 #include <hip/hip_runtime.h>
 
@@ -24,6 +27,25 @@ using namespace lbmib;
 namespace lbmib {
 namespace rt {
 
+// Storage of one recomputed segment (two of them alternate).
+struct AdjSet {
+  float* P = nullptr;           // [2][19][pstride] recompute populations
+  float4* mom = nullptr;        // [K][nodes]
+  double* pslab = nullptr;      // [K+1][3][nm]
+  BeadState* bslab = nullptr;   // [K+1][nbeads]
+  float* fslab = nullptr;       // [K][3][nm] marker forces
+  float* Fslab = nullptr;       // [K][3][pstride] force density of each step (active tiles)
+  int* stslab = nullptr;        // [K][ntiles] tile stamps of each step
+  float* u = nullptr;           // [3][pstride] velocity at forced nodes
+  float* U = nullptr;           // [3][nm]
+  int64_t* step = nullptr;      // step index of the segment's first step
+  // near-block marks of every segment step (blocks of kScBlock nodes): flags
+  // [K+1][kNearSlots][nsc], lists [K+1][2][max_near], counts [K+1][2]; entry i holds
+  // the marks step i's launches read (made by step i-1's bead statistics)
+  int *nflag = nullptr, *nlist = nullptr, *ncount = nullptr, *count_sink = nullptr;
+  BeadState* bsink = nullptr;   // bead statistics of the segment-start marking
+};
+
 // Reverse-sweep buffers, kept on the handle between calls.
 struct AdjWork {
   int64_t nck = 0;
@@ -32,37 +54,31 @@ struct AdjWork {
   float* ck_pop = nullptr;      // [nck][19][pstride]
   double* ck_pos = nullptr;     // [nck][3][nm]
   BeadState* ck_bst = nullptr;  // [nck][nbeads]
-  float* P = nullptr;           // [2][19][pstride] recompute populations
+  AdjSet set[2];
   float* L = nullptr;           // [2][19][pstride] adjoint populations
-  float4* mom = nullptr;        // [K][nodes]
-  double* pslab = nullptr;      // [K+1][3][nm]
-  BeadState* bslab = nullptr;   // [K+1][nbeads]
-  float* fslab = nullptr;       // [K][3][nm] marker forces
-  float* Fslab = nullptr;       // [K][3][pstride] force density of each step (active tiles)
-  int* stslab = nullptr;        // [K][ntiles] tile stamps of each step
-  float *u = nullptr, *lu = nullptr, *lF = nullptr;  // [3][pstride]
-  float* U = nullptr;           // [3][nm]
-  int64_t* step = nullptr;
+  float *lu = nullptr, *lF = nullptr;  // [3][pstride]
   int* overflow = nullptr;
-  // near-block marks of every segment step (blocks of kScBlock nodes): flags
-  // [K+1][kNearSlots][nsc], lists [K+1][2][max_near], counts [K+1][2]; entry i holds
-  // the marks step i's launches read (made by step i-1's bead statistics)
   int nsc = 0, max_near = 0;
-  int *nflag = nullptr, *nlist = nullptr, *ncount = nullptr, *count_sink = nullptr;
-  BeadState* bsink = nullptr;   // bead statistics of the segment-start marking
-  hipStream_t side = nullptr;
-  hipEvent_t ev[10] = {};
-  std::map<int64_t, hipGraphExec_t> graphs;  // segment graphs by 2 * length + parity
+  hipStream_t side = nullptr;            // reverse sweep: side stream (main: the handle's)
+  hipStream_t rmain = nullptr, rside = nullptr;  // recompute
+  hipEvent_t ev[12] = {};  // 0-3, 8, 9: recompute; 4-7, 10, 11: reverse
+  hipEvent_t rec_done[2] = {}, rev_done[2] = {}, start = nullptr;
+  std::map<int64_t, hipGraphExec_t> rgraphs, vgraphs;  // by (length, parity, set)
   double *lr = nullptr, *lfm = nullptr, *ltmp = nullptr, *bsum = nullptr, *grad = nullptr;
   float* lr32 = nullptr;
 
   ~AdjWork() {
-    if (side) (void)hipStreamSynchronize(side);
-    for (auto& kv : graphs)
-      if (kv.second) (void)hipGraphExecDestroy(kv.second);
+    for (hipStream_t q : {side, rmain, rside})
+      if (q) (void)hipStreamSynchronize(q);
+    for (auto* g : {&rgraphs, &vgraphs})
+      for (auto& kv : *g)
+        if (kv.second) (void)hipGraphExecDestroy(kv.second);
     for (hipEvent_t e : ev)
       if (e) (void)hipEventDestroy(e);
-    if (side) (void)hipStreamDestroy(side);
+    for (hipEvent_t e : {rec_done[0], rec_done[1], rev_done[0], rev_done[1], start})
+      if (e) (void)hipEventDestroy(e);
+    for (hipStream_t q : {side, rmain, rside})
+      if (q) (void)hipStreamDestroy(q);
     for (void* p : allocs) (void)hipFree(p);
   }
   template <class T>
@@ -92,19 +108,6 @@ int ensure_work(lbm_handle* h, int64_t nck, int K) {
   w->ck_pop = w->alloc<float>((size_t)nck * kQ * ps, rc);
   w->ck_pos = w->alloc<double>((size_t)nck * 3 * nm, rc);
   w->ck_bst = w->alloc<BeadState>((size_t)nck * nb, rc);
-  w->P = w->alloc<float>(2 * kQ * ps, rc);
-  w->L = w->alloc<float>(2 * kQ * ps, rc);
-  w->mom = w->alloc<float4>((size_t)K * h->nodes, rc);
-  w->pslab = w->alloc<double>((size_t)(K + 1) * 3 * nm, rc);
-  w->bslab = w->alloc<BeadState>((size_t)(K + 1) * nb, rc);
-  w->fslab = w->alloc<float>((size_t)K * 3 * nm, rc);
-  w->Fslab = w->alloc<float>((size_t)K * 3 * ps, rc);
-  w->stslab = w->alloc<int>((size_t)K * h->ntiles, rc);
-  w->u = w->alloc<float>(3 * ps, rc);
-  w->lu = w->alloc<float>(3 * ps, rc);
-  w->lF = w->alloc<float>(3 * ps, rc);
-  w->U = w->alloc<float>(3 * nm, rc);
-  w->step = w->alloc<int64_t>(1, rc);
   // near-block bound of the scratch launches (as set_near_bounds, blocks of kScBlock)
   w->nsc = (int)((h->nodes + kScBlock - 1) / kScBlock);
   int64_t mx = 0;
@@ -116,11 +119,26 @@ int ensure_work(lbm_handle* h, int64_t nck, int K) {
     mx += sy * sz * (sx / kScBlock + 2);
   }
   w->max_near = (int)std::max<int64_t>(1, std::min<int64_t>(mx, w->nsc));
-  w->nflag = w->alloc<int>((size_t)(K + 1) * kNearSlots * w->nsc, rc);
-  w->nlist = w->alloc<int>((size_t)(K + 1) * 2 * w->max_near, rc);
-  w->ncount = w->alloc<int>((size_t)(K + 1) * 2, rc);
-  w->count_sink = w->alloc<int>(2, rc);
-  w->bsink = w->alloc<BeadState>(nb, rc);
+  for (AdjSet& S : w->set) {
+    S.P = w->alloc<float>(2 * kQ * ps, rc);
+    S.mom = w->alloc<float4>((size_t)K * h->nodes, rc);
+    S.pslab = w->alloc<double>((size_t)(K + 1) * 3 * nm, rc);
+    S.bslab = w->alloc<BeadState>((size_t)(K + 1) * nb, rc);
+    S.fslab = w->alloc<float>((size_t)K * 3 * nm, rc);
+    S.Fslab = w->alloc<float>((size_t)K * 3 * ps, rc);
+    S.stslab = w->alloc<int>((size_t)K * h->ntiles, rc);
+    S.u = w->alloc<float>(3 * ps, rc);
+    S.U = w->alloc<float>(3 * nm, rc);
+    S.step = w->alloc<int64_t>(1, rc);
+    S.nflag = w->alloc<int>((size_t)(K + 1) * kNearSlots * w->nsc, rc);
+    S.nlist = w->alloc<int>((size_t)(K + 1) * 2 * w->max_near, rc);
+    S.ncount = w->alloc<int>((size_t)(K + 1) * 2, rc);
+    S.count_sink = w->alloc<int>(2, rc);
+    S.bsink = w->alloc<BeadState>(nb, rc);
+  }
+  w->L = w->alloc<float>(2 * kQ * ps, rc);
+  w->lu = w->alloc<float>(3 * ps, rc);
+  w->lF = w->alloc<float>(3 * ps, rc);
   w->overflow = w->alloc<int>(1, rc);
   w->lr = w->alloc<double>(3 * nm, rc);
   w->lfm = w->alloc<double>(3 * nm, rc);
@@ -128,9 +146,12 @@ int ensure_work(lbm_handle* h, int64_t nck, int K) {
   w->bsum = w->alloc<double>(4 * nb, rc);
   w->grad = w->alloc<double>(4, rc);
   w->lr32 = w->alloc<float>(3 * nm, rc);
-  if (!rc) rc = h->hip(hipStreamCreate(&w->side), "hipStreamCreate");
+  for (hipStream_t* q : {&w->side, &w->rmain, &w->rside})
+    if (!rc) rc = h->hip(hipStreamCreate(q), "hipStreamCreate");
   for (hipEvent_t& e : w->ev)
     if (!rc) rc = h->hip(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreateWithFlags");
+  for (hipEvent_t* e : {&w->rec_done[0], &w->rec_done[1], &w->rev_done[0], &w->rev_done[1], &w->start})
+    if (!rc) rc = h->hip(hipEventCreateWithFlags(e, hipEventDisableTiming), "hipEventCreateWithFlags");
   if (rc) {
     delete w;
     return h->fail(rc, "adjoint workspace allocation failed");
@@ -141,11 +162,11 @@ int ensure_work(lbm_handle* h, int64_t nck, int K) {
 
 // The scratch view reading (and, for bead statistics, writing) the near-block
 // marks of segment step i.
-Dev near_view(const Dev& base, const AdjWork& w, int i) {
+Dev near_view(const Dev& base, const AdjWork& w, const AdjSet& S, int i) {
   Dev d = base;
-  d.near = w.nflag + (size_t)i * kNearSlots * w.nsc;
-  d.near_list = w.nlist + (size_t)i * 2 * w.max_near;
-  d.near_count = w.ncount + (size_t)i * 2;
+  d.near = S.nflag + (size_t)i * kNearSlots * w.nsc;
+  d.near_list = S.nlist + (size_t)i * 2 * w.max_near;
+  d.near_count = S.ncount + (size_t)i * 2;
   return d;
 }
 
@@ -159,93 +180,107 @@ Dev with_near(Dev d, const Dev& n) {
 // Advection of segment step i: markers of pslab[i] into pslab[i+1]; the
 // near-count reset of the advection kernel goes to a sink (every entry's
 // counts are cleared at segment start).
-Dev advect_view(const Dev& base, const AdjWork& w, int i, size_t nm) {
+Dev advect_view(const Dev& base, const AdjSet& S, int i, size_t nm) {
   Dev d = base;
   d.sub = i + 1;
-  d.pos = w.pslab + i * 3 * nm;
-  d.pos_next = w.pslab + (i + 1) * 3 * nm;
-  d.near_count = w.count_sink;
+  d.pos = S.pslab + i * 3 * nm;
+  d.pos_next = S.pslab + (i + 1) * 3 * nm;
+  d.near_count = S.count_sink;
   return d;
 }
 
-// Everything of one segment after its checkpoint is in place: near marks of
-// its first step, the recompute, the reverse sweep.  Depends on the segment
-// only through its length m and the parity par of its first step.
-void enqueue_segment(lbm_handle* h, AdjWork& w, const Dev& dS, Adj a, int m, int par, int nblocks) {
+// The state view of a segment set: its populations, velocity, marker
+// velocities and step counter.
+Dev set_view(const Dev& dS, const AdjSet& S, size_t popn) {
+  Dev d = dS;
+  d.pop[0] = S.P;
+  d.pop[1] = S.P + popn;
+  d.u = S.u;
+  d.step = S.step;
+  d.U = S.U;
+  return d;
+}
+
+// Recompute of one segment from its checkpoint (already in the set), on the
+// streams s (main) and S2 (side): near marks of its first step, then the
+// steps as lbm_step's concurrent schedule -- the side stream advects step
+// i-1 and runs step i's bead statistics, forces, spreading and near-block
+// launch (after the bulk launch of step i-1), the main stream the bulk launch
+// of step i (after the near-block launch of step i-1).  Step i reads the
+// markers of pslab[i], advects them into pslab[i+1], writes its bead
+// statistics to bslab[i+1] taking the previous centres (the volume's
+// reference point) from bslab[i], and marks the near blocks of step i+1 into
+// entry i+1.
+void enqueue_recompute(lbm_handle* h, AdjWork& w, const AdjSet& St, const Dev& dS, int m, int nblocks,
+                       hipStream_t s, hipStream_t S2) {
   const size_t ps = (size_t)h->pstride, nm = (size_t)h->nm, nb = h->beads.size();
-  const size_t popn = kQ * ps;
-  hipStream_t s = h->stream;
-  // near marks of the segment's first step from the checkpoint's markers (into entry 0),
-  // bead statistics discarded
+  hipEvent_t* ev = w.ev;
   {
-    Dev d = near_view(dS, w, 0);
-    d.pos = w.pslab;
-    d.bstate_prev = w.bslab;
-    d.bstate = w.bsink;
+    // near marks of the segment's first step from the checkpoint's markers
+    // (into entry 0), bead statistics discarded
+    Dev d = near_view(dS, w, St, 0);
+    d.pos = St.pslab;
+    d.bstate_prev = St.bslab;
+    d.bstate = St.bsink;
     launch_bead_stats(d, -1, s);
   }
-  hipStream_t S = w.side;
-  hipEvent_t* ev = w.ev;
   (void)hipEventRecord(ev[8], s);
-  (void)hipStreamWaitEvent(S, ev[8], 0);
-  // Recompute, as lbm_step's concurrent schedule: the side stream advects
-  // step i-1, then runs step i's bead statistics, forces, spreading and
-  // near-block launch (after the bulk launch of step i-1); the main stream
-  // runs the bulk launch of step i (after the near-block launch of step i-1).
-  // Step i reads the markers of pslab[i], advects them into pslab[i+1],
-  // writes its bead statistics to bslab[i+1] taking the previous centres
-  // (the volume's reference point) from bslab[i], and marks the near blocks
-  // of step i+1 into entry i+1.
+  (void)hipStreamWaitEvent(S2, ev[8], 0);
   for (int i = 0; i < m; ++i) {
     Dev d = dS;
     d.sub = i;
-    d.pos = w.pslab + i * 3 * nm;
-    d.bstate_prev = w.bslab + i * nb;
-    d.bstate = w.bslab + (i + 1) * nb;
-    d.fm = w.fslab + i * 3 * nm;
-    d.F = w.Fslab + (size_t)i * 3 * ps;
-    d.stamp = w.stslab + (size_t)i * h->ntiles;
-    d.mom = w.mom + (size_t)i * h->nodes;
+    d.pos = St.pslab + i * 3 * nm;
+    d.bstate_prev = St.bslab + i * nb;
+    d.bstate = St.bslab + (i + 1) * nb;
+    d.fm = St.fslab + i * 3 * nm;
+    d.F = St.Fslab + (size_t)i * 3 * ps;
+    d.stamp = St.stslab + (size_t)i * h->ntiles;
+    d.mom = St.mom + (size_t)i * h->nodes;
     hipEvent_t bulk_now = ev[i & 1], bulk_prev = ev[(i + 1) & 1];
     hipEvent_t near_now = ev[2 + (i & 1)], near_prev = ev[2 + ((i + 1) & 1)];
-    if (i > 0) launch_interp_advance(advect_view(dS, w, i - 1, nm), S);
-    const Dev dm = with_near(d, near_view(dS, w, i + 1));
-    launch_bead_stats(dm, 0, S);
-    launch_vertex_forces(dm, S);
-    launch_spread(dm, S);
-    const Dev dr = with_near(d, near_view(dS, w, i));
+    if (i > 0) launch_interp_advance(advect_view(dS, St, i - 1, nm), S2);
+    const Dev dm = with_near(d, near_view(dS, w, St, i + 1));
+    launch_bead_stats(dm, 0, S2);
+    launch_vertex_forces(dm, S2);
+    launch_spread(dm, S2);
+    const Dev dr = with_near(d, near_view(dS, w, St, i));
     if (i > 0) (void)hipStreamWaitEvent(s, near_prev, 0);
     launch_stream_collide_mom(dr, kLaunchBulk, nblocks, s);
     (void)hipEventRecord(bulk_now, s);
-    if (i > 0) (void)hipStreamWaitEvent(S, bulk_prev, 0);
-    launch_stream_collide_mom(dr, kLaunchActive, nblocks, S);
-    (void)hipEventRecord(near_now, S);
+    if (i > 0) (void)hipStreamWaitEvent(S2, bulk_prev, 0);
+    launch_stream_collide_mom(dr, kLaunchActive, nblocks, S2);
+    (void)hipEventRecord(near_now, S2);
   }
-  (void)hipEventRecord(ev[8], s);
-  (void)hipStreamWaitEvent(S, ev[8], 0);
-  launch_interp_advance(advect_view(dS, w, m - 1, nm), S);
-  (void)hipEventRecord(ev[9], S);
+  launch_interp_advance(advect_view(dS, St, m - 1, nm), S2);
+  (void)hipEventRecord(ev[9], S2);
   (void)hipStreamWaitEvent(s, ev[9], 0);
-  // Reverse steps of the segment, last to first.  The main stream runs the adjoint
-  // collide of the blocks away from the swimmers; the side stream spreads
-  // lambda_u, runs the near blocks, then the marker adjoints.  Bulk i reads
-  // (and its parity is read by) near-block launch i+1; near-block launch i
-  // likewise pairs with bulk i+1.
-  (void)hipEventRecord(ev[8], s);
-  (void)hipStreamWaitEvent(S, ev[8], 0);
+}
+
+// Reverse steps of a segment, last to first, on the streams s (main) and S2
+// (side).  The main stream runs the adjoint collide of the blocks away from
+// the swimmers; the side stream spreads lambda_u, runs the near blocks, then
+// the marker adjoints.  Bulk i reads (and its parity is read by) near-block
+// launch i+1; near-block launch i likewise pairs with bulk i+1.
+void enqueue_reverse(lbm_handle* h, AdjWork& w, const AdjSet& St, const Dev& dS, Adj a, int m, int par,
+                     int nblocks, hipStream_t s, hipStream_t S2) {
+  const size_t ps = (size_t)h->pstride, nm = (size_t)h->nm, nb = h->beads.size();
+  const size_t popn = kQ * ps;
+  hipEvent_t* ev = w.ev;
+  (void)hipEventRecord(ev[10], s);
+  (void)hipStreamWaitEvent(S2, ev[10], 0);
   for (int i = m - 1; i >= 0; --i) {
     const int n = par + i;  // the parity of the step index is all that is used
     Dev d = dS;
     d.sub = i;
-    d.pos = w.pslab + i * 3 * nm;
-    d.bstate = w.bslab + (i + 1) * nb;
-    d.fm = w.fslab + i * 3 * nm;
-    d.F = w.Fslab + (size_t)i * 3 * ps;  // F_n, kept by the recompute
-    d.stamp = w.stslab + (size_t)i * h->ntiles;
-    const Dev dr = with_near(d, near_view(dS, w, i));
+    d.pos = St.pslab + i * 3 * nm;
+    d.bstate = St.bslab + (i + 1) * nb;
+    d.fm = St.fslab + i * 3 * nm;
+    d.F = St.Fslab + (size_t)i * 3 * ps;  // F_n, kept by the recompute
+    d.stamp = St.stslab + (size_t)i * h->ntiles;
+    const Dev dr = with_near(d, near_view(dS, w, St, i));
     a.Lsrc = w.L + ((n + 1) & 1) * popn;
     a.Ldst = w.L + (n & 1) * popn;
-    a.mom = w.mom + (size_t)i * h->nodes;
+    a.mom = St.mom + (size_t)i * h->nodes;
     const bool first = i == m - 1;
     hipEvent_t bulk_now = ev[4 + (i & 1)], bulk_prev = ev[4 + ((i + 1) & 1)];
     hipEvent_t near_now = ev[6 + (i & 1)], near_prev = ev[6 + ((i + 1) & 1)];
@@ -255,33 +290,33 @@ void enqueue_segment(lbm_handle* h, AdjWork& w, const Dev& dS, Adj a, int m, int
     Dev dl = d;
     dl.fm = w.lr32;
     dl.F = w.lu;
-    launch_spread(dl, S);  // lambda_u = S(r_n) lambda_r(n+1), same tiles as F_n
-    if (!first) (void)hipStreamWaitEvent(S, bulk_prev, 0);
-    launch_adj_collide(dr, a, kLaunchActive, nblocks, S);
-    (void)hipEventRecord(near_now, S);
-    launch_adj_gather(d, a, S);
-    launch_adj_bead(d, a, S);
-    launch_adj_tangent(d, a, S);
+    launch_spread(dl, S2);  // lambda_u = S(r_n) lambda_r(n+1), same tiles as F_n
+    if (!first) (void)hipStreamWaitEvent(S2, bulk_prev, 0);
+    launch_adj_collide(dr, a, kLaunchActive, nblocks, S2);
+    (void)hipEventRecord(near_now, S2);
+    launch_adj_gather(d, a, S2);
+    launch_adj_bead(d, a, S2);
+    launch_adj_tangent(d, a, S2);
   }
-  (void)hipEventRecord(ev[9], S);
-  (void)hipStreamWaitEvent(s, ev[9], 0);
+  (void)hipEventRecord(ev[11], S2);
+  (void)hipStreamWaitEvent(s, ev[11], 0);
 }
 
-// Segments replay captured HIP graphs (one per length and parity) when the
-// handle steps with graphs, else enqueue directly.
-int enqueue_or_replay(lbm_handle* h, AdjWork& w, const Dev& dS, const Adj& a, int m, int par, int nblocks) {
+// Enqueue (or replay the captured graph of) one part on its main stream.
+template <class F>
+int enqueue_or_replay(lbm_handle* h, std::map<int64_t, hipGraphExec_t>& graphs, int64_t key, hipStream_t s,
+                      F&& enqueue) {
   if (!h->use_graphs) {
-    enqueue_segment(h, w, dS, a, m, par, nblocks);
+    enqueue();
     return h->hip(hipGetLastError(), "adjoint launch");
   }
-  const int64_t key = 2 * (int64_t)m + par;
-  hipGraphExec_t& g = w.graphs[key];
+  hipGraphExec_t& g = graphs[key];
   if (!g) {
     hipGraph_t graph = nullptr;
-    int rc = h->hip(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    int rc = h->hip(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
     if (rc) return rc;
-    enqueue_segment(h, w, dS, a, m, par, nblocks);
-    rc = h->hip(hipStreamEndCapture(h->stream, &graph), "hipStreamEndCapture");
+    enqueue();
+    rc = h->hip(hipStreamEndCapture(s, &graph), "hipStreamEndCapture");
     if (!rc) rc = h->hip(hipGraphInstantiate(&g, graph, nullptr, nullptr, 0), "hipGraphInstantiate");
     if (graph) (void)hipGraphDestroy(graph);
     if (rc) {
@@ -289,12 +324,12 @@ int enqueue_or_replay(lbm_handle* h, AdjWork& w, const Dev& dS, const Adj& a, in
       return rc;
     }
   }
-  return h->hip(hipGraphLaunch(g, h->stream), "hipGraphLaunch");
+  return h->hip(hipGraphLaunch(g, s), "hipGraphLaunch");
 }
 
-// Copy on the handle's stream.
-int dcopy(lbm_handle* h, void* dst, const void* src, size_t bytes) {
-  return h->hip(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, h->stream), "hipMemcpyAsync");
+// Copy on stream s.
+int dcopy(lbm_handle* h, void* dst, const void* src, size_t bytes, hipStream_t s) {
+  return h->hip(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s), "hipMemcpyAsync");
 }
 
 int run(lbm_handle* h, const lbm_adjoint_desc* ad, double* J, double* grad) {
@@ -317,9 +352,9 @@ int run(lbm_handle* h, const lbm_adjoint_desc* ad, double* J, double* grad) {
   const int64_t t0 = h->host_step;
   for (int64_t c = 0; c < nck; ++c) {
     const int64_t n0 = t0 + c * K, m = std::min<int64_t>(K, T - c * K);
-    rc = dcopy(h, w.ck_pop + c * popn, h->pop[n0 & 1], sizeof(float) * popn);
-    if (!rc) rc = dcopy(h, w.ck_pos + c * 3 * nm, h->d_pos, sizeof(double) * 3 * nm);
-    if (!rc) rc = dcopy(h, w.ck_bst + c * nb, h->d_bstate, sizeof(BeadState) * nb);
+    rc = dcopy(h, w.ck_pop + c * popn, h->pop[n0 & 1], sizeof(float) * popn, s);
+    if (!rc) rc = dcopy(h, w.ck_pos + c * 3 * nm, h->d_pos, sizeof(double) * 3 * nm, s);
+    if (!rc) rc = dcopy(h, w.ck_bst + c * nb, h->d_bstate, sizeof(BeadState) * nb, s);
     if (!rc) rc = lbm_step(h, m);
     if (rc) return rc;
   }
@@ -329,11 +364,6 @@ int run(lbm_handle* h, const lbm_adjoint_desc* ad, double* J, double* grad) {
 
   // scratch views of the state for the recompute and the reverse sweep
   Dev dS = h->dev;
-  dS.pop[0] = w.P;
-  dS.pop[1] = w.P + popn;
-  dS.u = w.u;
-  dS.step = w.step;
-  dS.U = w.U;
   dS.overflow = w.overflow;
   dS.nsc = w.nsc;
   dS.sc_bs = kScBlock;
@@ -349,28 +379,58 @@ int run(lbm_handle* h, const lbm_adjoint_desc* ad, double* J, double* grad) {
   a.grad = w.grad;
   a.swimmer = ad->swimmer;
   rc = h->hip(hipMemsetAsync(w.L, 0, sizeof(float) * 2 * popn, s), "hipMemsetAsync");
-  if (!rc) rc = h->hip(hipMemsetAsync(w.stslab, 0x80, sizeof(int) * (size_t)K * h->ntiles, s), "hipMemsetAsync");
-  if (!rc)
-    rc = h->hip(hipMemsetAsync(w.nflag, 0x80, sizeof(int) * (size_t)(K + 1) * kNearSlots * w.nsc, s), "hipMemsetAsync");
+  for (const AdjSet& St : w.set) {
+    if (!rc) rc = h->hip(hipMemsetAsync(St.stslab, 0x80, sizeof(int) * (size_t)K * h->ntiles, s), "hipMemsetAsync");
+    if (!rc)
+      rc = h->hip(hipMemsetAsync(St.nflag, 0x80, sizeof(int) * (size_t)(K + 1) * kNearSlots * w.nsc, s),
+                  "hipMemsetAsync");
+  }
   if (!rc) rc = h->hip(hipMemsetAsync(w.overflow, 0, sizeof(int), s), "hipMemsetAsync");
   if (rc) return rc;
-  launch_adj_init(dS, a, s);
+  launch_adj_init(set_view(dS, w.set[0], popn), a, s);
   const int nblocks = (int)((h->nodes + kScBlock - 1) / kScBlock);
+  // the recompute streams start after everything above
+  rc = h->hip(hipEventRecord(w.start, s), "hipEventRecord");
+  if (!rc) rc = h->hip(hipStreamWaitEvent(w.rmain, w.start, 0), "hipStreamWaitEvent");
+  if (rc) return rc;
 
-  for (int64_t c = nck - 1; c >= 0; --c) {
+  // Recompute of segment c into set c % 2 on the recompute streams, after the
+  // reverse sweep that last read that set (segment c + 2).
+  auto recompute = [&](int64_t c) -> int {
+    const int k = (int)(c & 1);
+    const AdjSet& St = w.set[k];
     const int64_t n0 = t0 + c * K;
     const int m = (int)std::min<int64_t>(K, T - c * K);
-    rc = dcopy(h, w.P + (n0 & 1) * popn, w.ck_pop + c * popn, sizeof(float) * popn);
-    if (!rc) rc = dcopy(h, w.pslab, w.ck_pos + c * 3 * nm, sizeof(double) * 3 * nm);
-    if (!rc) rc = dcopy(h, w.bslab, w.ck_bst + c * nb, sizeof(BeadState) * nb);
-    if (!rc) rc = h->hip(hipMemsetAsync(w.ncount, 0, sizeof(int) * (size_t)(K + 1) * 2, s), "hipMemsetAsync");
-    if (rc) return rc;
-    launch_set_step(w.step, n0, s);
-    rc = enqueue_or_replay(h, w, dS, a, m, (int)(n0 & 1), nblocks);
-    if (rc) return rc;
-    rc = h->hip(hipGetLastError(), "adjoint launch");
-    if (rc) return rc;
+    hipStream_t r = w.rmain;
+    int e = LBM_OK;
+    if (c + 2 < nck) e = h->hip(hipStreamWaitEvent(r, w.rev_done[k], 0), "hipStreamWaitEvent");
+    if (!e) e = dcopy(h, St.P + (n0 & 1) * popn, w.ck_pop + c * popn, sizeof(float) * popn, r);
+    if (!e) e = dcopy(h, St.pslab, w.ck_pos + c * 3 * nm, sizeof(double) * 3 * nm, r);
+    if (!e) e = dcopy(h, St.bslab, w.ck_bst + c * nb, sizeof(BeadState) * nb, r);
+    if (!e) e = h->hip(hipMemsetAsync(St.ncount, 0, sizeof(int) * (size_t)(K + 1) * 2, r), "hipMemsetAsync");
+    if (e) return e;
+    launch_set_step(St.step, n0, r);
+    const Dev dv = set_view(dS, St, popn);
+    e = enqueue_or_replay(h, w.rgraphs, 4 * (int64_t)m + k, r,
+                          [&] { enqueue_recompute(h, w, St, dv, m, nblocks, r, w.rside); });
+    if (!e) e = h->hip(hipEventRecord(w.rec_done[k], r), "hipEventRecord");
+    return e;
+  };
+  rc = recompute(nck - 1);
+  for (int64_t c = nck - 1; c >= 0 && !rc; --c) {
+    if (c > 0) rc = recompute(c - 1);
+    if (rc) break;
+    const int k = (int)(c & 1);
+    const int64_t n0 = t0 + c * K;
+    const int m = (int)std::min<int64_t>(K, T - c * K);
+    rc = h->hip(hipStreamWaitEvent(s, w.rec_done[k], 0), "hipStreamWaitEvent");
+    if (rc) break;
+    const Dev dv = set_view(dS, w.set[k], popn);
+    rc = enqueue_or_replay(h, w.vgraphs, 4 * (int64_t)m + 2 * (int64_t)(n0 & 1) + k, s,
+                           [&] { enqueue_reverse(h, w, w.set[k], dv, a, m, (int)(n0 & 1), nblocks, s, w.side); });
+    if (!rc) rc = h->hip(hipEventRecord(w.rev_done[k], s), "hipEventRecord");
   }
+  if (rc) return rc;
   int ov = 0;
   rc = h->hip(hipMemcpyAsync(grad, w.grad, sizeof(double) * 4, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
   if (!rc) rc = h->hip(hipMemcpyAsync(&ov, w.overflow, sizeof(int), hipMemcpyDeviceToHost, s), "hipMemcpyAsync");

@@ -134,10 +134,10 @@ struct Dev {
   // h*4 + role, vertex ids x1 x2 x3 x4); element -1 = idle lane
   const int* lane_elem;  // [nm * 32]
   const int4* lane_v;    // [nm * 32]
-  // stream-collide blocks near the swimmers: flags near[parity][block] = step
-  // that marked the block, and per-parity block lists (near_list[parity][i],
-  // near_count[parity]); a block is near when it holds a node within two
-  // nodes of a bead's stencil region
+  // stream-collide blocks near the swimmers: flags near[step mod 3][block] =
+  // step that marked the block, and per-parity block lists
+  // (near_list[parity][i], near_count[parity]); a block is near when it holds
+  // a node within two nodes of a bead's stencil region
   int* near;
   int* near_list;
   int* near_count;
