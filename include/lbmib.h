@@ -245,8 +245,9 @@ typedef struct {
  * dJ/dalpha, dJ/dk (k scales both springs).  The forward run is ordinary
  * stepping, so on return the handle has advanced T steps exactly as lbm_step
  * would have taken it (unless `rewind`).  Device memory: 19*4 bytes per node
- * per checkpoint, 16 bytes per node per segment step, plus four population
- * sets.  The adjoint arithmetic is FP32 on the grid and FP64 on the markers
+ * per checkpoint; two segment buffers (the recompute of one segment runs
+ * beside the reverse sweep of the next) of 28 bytes per node per segment
+ * step ((rho, u) and the force density); six population sets.  The adjoint arithmetic is FP32 on the grid and FP64 on the markers
  * and parameter sums.  Single-box handles with FP32 storage and Guo forcing
  * only.  Errors: LBM_EINVAL (bad descriptor, batch, FP16 storage, Shan-Chen
  * forcing), LBM_ENOMEM, LBM_EDEVICE, LBM_EOVERFLOW. */
@@ -255,8 +256,9 @@ int lbm_adjoint(lbm_handle* h, const lbm_adjoint_desc* desc, double* J, double g
 /* ---- checkpoint ---------------------------------------------------------------- */
 /* Write / restore the full dynamic state (populations, forces, tile stamps,
  * markers, step counter) to / from a file.  Restoring needs a handle created
- * with the same grid, options and swimmers; the restart is bit-exact.
- * Errors: LBM_EIO, LBM_EINVAL (mismatched handle). */
+ * with the same grid, options and swimmers, and a file of the same format
+ * version (written into its header); the restart is bit-exact.
+ * Errors: LBM_EIO, LBM_EINVAL (mismatched handle or format version). */
 int lbm_save(lbm_handle* h, const char* path);
 int lbm_load(lbm_handle* h, const char* path);
 
@@ -270,9 +272,10 @@ int lbm_kernel_time(lbm_handle* h, double* ms, int64_t* launches);
  * nodes; whether workgroups are remapped so that each of the 8 XCDs streams
  * one contiguous range of the grid; and, with swimmers, `resident` > 0 makes
  * the launch that runs concurrently with the immersed-boundary kernels
- * persistent with that many workgroups per compute unit (0: one workgroup
- * per block; -1: no concurrency, the immersed-boundary kernels then one
- * full-grid launch).  Results are bitwise identical for every shape.
+ * persistent with that many workgroups per compute unit, each walking one
+ * XCD's contiguous range when remapped and the grid in strides otherwise (0:
+ * one workgroup per block; -1: no concurrency, the immersed-boundary kernels
+ * then one full-grid launch).  Results are bitwise identical for every shape.
  * Errors: LBM_EINVAL. */
 int lbm_set_stream_collide_launch(lbm_handle* h, int block, int xcd_remap, int resident);
 /* Algorithmic bytes one stream-collide launch moves (19 populations read and
