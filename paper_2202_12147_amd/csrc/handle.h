@@ -93,7 +93,7 @@ struct lbm_handle {
   int *d_near = nullptr, *d_near_list = nullptr, *d_near_count = nullptr;
   bool need_prologue = true;
   hipStream_t side = nullptr;      // IBM chain, forked from `stream` every step
-  std::vector<hipEvent_t> fork_join;
+  std::vector<hipEvent_t> step_events;  // per chunk step: bulk done, near blocks done; + one fork
   double *d_partial = nullptr, *d_out = nullptr, *d_centres = nullptr;
   std::vector<void*> allocs;
 

@@ -364,8 +364,8 @@ int upload(lbm_handle* h) {
   if (!h->swimmers.empty()) {
     rc = h->hip(hipStreamCreate(&h->side), "hipStreamCreate");
     if (rc) return rc;
-    h->fork_join.resize(2 * kGraphChunk + 1);
-    for (auto& e : h->fork_join) {
+    h->step_events.resize(2 * kGraphChunk + 1);
+    for (auto& e : h->step_events) {
       rc = h->hip(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreateWithFlags");
       if (rc) return rc;
     }
@@ -432,12 +432,12 @@ void enqueue_steps(lbm_handle* h, int64_t count) {
   // step n; the bulk launch of step n needs the near blocks of step n - 1.
   // Each stream waits on the other with a lag of one step, so in the steady
   // state the bulk launches run back to back.
-  hipEvent_t fork = h->fork_join[2 * kGraphChunk];
+  hipEvent_t fork = h->step_events[2 * kGraphChunk];
   (void)hipEventRecord(fork, h->stream);
   (void)hipStreamWaitEvent(h->side, fork, 0);
   hipEvent_t prev_bulk = nullptr, prev_near = nullptr;
   for (int64_t i = 0; i < count; ++i) {
-    hipEvent_t ev_bulk = h->fork_join[2 * (i % kGraphChunk)], ev_near = h->fork_join[2 * (i % kGraphChunk) + 1];
+    hipEvent_t ev_bulk = h->step_events[2 * (i % kGraphChunk)], ev_near = h->step_events[2 * (i % kGraphChunk) + 1];
     d.sub = (int)i;
     if (i > 0) launch_interp_advance(d, h->side);
     launch_bead_stats(d, 0, h->side);
@@ -699,7 +699,7 @@ int lbm_destroy(lbm_handle* h) {
   if (h->g_chunk) (void)hipGraphExecDestroy(h->g_chunk);
   if (h->g_one) (void)hipGraphExecDestroy(h->g_one);
   for (auto e : h->ev_pool) (void)hipEventDestroy(e);
-  for (auto e : h->fork_join) (void)hipEventDestroy(e);
+  for (auto e : h->step_events) (void)hipEventDestroy(e);
   if (h->side) (void)hipStreamDestroy(h->side);
   rt::adjoint_release(h);
   for (void* p : h->allocs) (void)hipFree(p);
