@@ -25,7 +25,7 @@ PEAK_HBM_GBS = 8000.0
 # order (no XCD remap) runs the full-grid launch at 54 us against 58 us
 # remapped, while the 1024x256x256 box is 2 % faster remapped
 MAIN_LAUNCH = (256, False, 2)
-FP16_LAUNCH = (256, False, 0)
+FP16_LAUNCH = (256, False, 2)
 BATCH_LAUNCH = (512, False, 0)
 BOX_LAUNCH = (256, True, 0)
 KERNEL_LAUNCH = (256, False, -1)  # serial order: full-grid launch for the roofline
