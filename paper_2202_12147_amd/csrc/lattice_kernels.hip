@@ -44,14 +44,16 @@ template <>
 struct PopIO<kFp32> {
   using T = float;
   __device__ static inline float ld(const float* p, int, float) { return __builtin_nontemporal_load(p); }
-  __device__ static inline void st(float* p, int, float v, float) { __builtin_nontemporal_store(v, p); }
+  __device__ static inline void st(float* p, int, float v, float) { stream_store(p, v); }
 };
 
 template <>
 struct PopIO<kFp16> {
   using T = __half;
   __device__ static inline float ld(const __half* p, int, float inv) { return __half2float(*p) * inv; }
-  __device__ static inline void st(__half* p, int, float v, float scale) { *p = __float2half_rn(v * scale); }
+  __device__ static inline void st(__half* p, int, float v, float scale) {
+    stream_store(reinterpret_cast<unsigned short*>(p), __half_as_ushort(__float2half_rn(v * scale)));
+  }
 };
 
 // Unshifted storage of f itself (rounded at the scale of w_q ~ 1/3): the
@@ -62,7 +64,7 @@ struct PopIO<kFp32Plain> {
   __device__ static inline float ld(const float* p, int q, float) {
     return __builtin_nontemporal_load(p) - weight(q);
   }
-  __device__ static inline void st(float* p, int q, float v, float) { __builtin_nontemporal_store(v + weight(q), p); }
+  __device__ static inline void st(float* p, int q, float v, float) { stream_store(p, v + weight(q)); }
 };
 
 // Offsets (in nodes, periodic wrap folded in) of the six face neighbours.
