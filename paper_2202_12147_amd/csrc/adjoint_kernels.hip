@@ -162,8 +162,13 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(Dev d, Adj a, int nblock
   const float cq[kQ] = {0.0f,       btx,        -btx,       bty,        -bty,       btz,        -btz,
                         btx + bty,  -btx - bty, btx - bty,  bty - btx,  btx + btz,  -btx - btz, btx - btz,
                         btz - btx,  bty + btz,  -bty - btz, bty - btz,  btz - bty};
+  if (d.wt_stores) {
 #pragma unroll
-  for (int q = 0; q < kQ; ++q) stream_store(a.Ldst + pop_index(q, base), k1 * L[q] + a0 + cq[q]);
+    for (int q = 0; q < kQ; ++q) stream_store(a.Ldst + pop_index(q, base), k1 * L[q] + a0 + cq[q]);
+  } else {
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) __builtin_nontemporal_store(k1 * L[q] + a0 + cq[q], a.Ldst + pop_index(q, base));
+  }
 }
 
 // ---- transposed spreading and interpolation -----------------------------------------

@@ -29,19 +29,23 @@ constexpr int kScBlock = 256;  // stream-collide threads per block
 // keep two (step parity).
 constexpr int kNearSlots = 3;
 
-// Store of a streamed population value: a relaxed atomic store at system
-// scope, which the compiler issues as a plain global store with the
-// system-coherence bits (written through, no L2 line allocated).  For the
-// 19-way streaming writes of a lattice sweep this leaves the L2 to the pulls
-// and to the immersed-boundary kernels running beside the sweep: on MI355X a
-// 128^3 FP32 sweep takes 45.5 us with it against 54.3 us with non-temporal
-// stores, and 45.9 us with plain stores, which slow the concurrent kernels.
+// Store of a streamed population value, written through: a relaxed atomic
+// store at system scope, which the compiler issues as a plain global store
+// with the system-coherence bits (no L2 line allocated).  For the 19-way
+// streaming writes of a lattice sweep this leaves the L2 to the pulls and to
+// the immersed-boundary kernels running beside the sweep.  On MI355X it pays
+// while the two population sets are of the order of the 256 MB last-level
+// cache (128^3 FP32: 45.5 us per sweep against 54.3 us with non-temporal
+// stores; 45.9 us with plain stores, which slow the concurrent kernels) and
+// costs 6 % on a 7.7 GB batch, so handles use it up to kWriteThroughBytes of
+// population storage (Dev::wt_stores) and non-temporal stores above.
 __device__ inline void stream_store(float* p, float v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 __device__ inline void stream_store(unsigned short* p, unsigned short v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
+constexpr int64_t kWriteThroughBytes = int64_t(1) << 30;  // both population sets
 __host__ __device__ inline int near_slot(int64_t v) {
   const int r = (int)(v % kNearSlots);
   return r < 0 ? r + kNearSlots : r;
@@ -156,6 +160,7 @@ struct Dev {
   int* near_list;
   int* near_count;
   int max_near, nsc, sc_bs;
+  int wt_stores;          // population stores written through (stream_store) or non-temporal
   const int* tile_box;   // tile -> box (batches only)
   int* overflow;         // set when a bead region outgrows its reserved tiles
   int spread_blocks;

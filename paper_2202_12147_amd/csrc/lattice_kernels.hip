@@ -44,14 +44,16 @@ template <>
 struct PopIO<kFp32> {
   using T = float;
   __device__ static inline float ld(const float* p, int, float) { return __builtin_nontemporal_load(p); }
-  __device__ static inline void st(float* p, int, float v, float) { stream_store(p, v); }
+  __device__ static inline void st(float* p, int, float v, float) { __builtin_nontemporal_store(v, p); }
+  __device__ static inline void st_wt(float* p, int, float v, float) { stream_store(p, v); }
 };
 
 template <>
 struct PopIO<kFp16> {
   using T = __half;
   __device__ static inline float ld(const __half* p, int, float inv) { return __half2float(*p) * inv; }
-  __device__ static inline void st(__half* p, int, float v, float scale) {
+  __device__ static inline void st(__half* p, int, float v, float scale) { *p = __float2half_rn(v * scale); }
+  __device__ static inline void st_wt(__half* p, int, float v, float scale) {
     stream_store(reinterpret_cast<unsigned short*>(p), __half_as_ushort(__float2half_rn(v * scale)));
   }
 };
@@ -64,7 +66,8 @@ struct PopIO<kFp32Plain> {
   __device__ static inline float ld(const float* p, int q, float) {
     return __builtin_nontemporal_load(p) - weight(q);
   }
-  __device__ static inline void st(float* p, int q, float v, float) { stream_store(p, v + weight(q)); }
+  __device__ static inline void st(float* p, int q, float v, float) { __builtin_nontemporal_store(v + weight(q), p); }
+  __device__ static inline void st_wt(float* p, int q, float v, float) { stream_store(p, v + weight(q)); }
 };
 
 // Offsets (in nodes, periodic wrap folded in) of the six face neighbours.
@@ -211,8 +214,13 @@ __device__ inline void sc_node(const Dev& d, const Box& B, int x, int y, int z, 
   collide_pair(g[15], g[16], kW2, om, m.drho, m.rho, usq15, ey + ez, src_a, uy + uz, Fy + Fz, uf);
   collide_pair(g[17], g[18], kW2, om, m.drho, m.rho, usq15, ey - ez, src_a, uy - uz, Fy - Fz, uf);
   T* const bq = dst + (base / kPopBlock) * (int64_t)(kQ * kPopBlock) + (int)(base % kPopBlock);
+  if (d.wt_stores) {
 #pragma unroll
-  for (int q = 0; q < kQ; ++q) IO::st(bq + q * kPopBlock, q, g[q], d.fp16_scale);
+    for (int q = 0; q < kQ; ++q) IO::st_wt(bq + q * kPopBlock, q, g[q], d.fp16_scale);
+  } else {
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) IO::st(bq + q * kPopBlock, q, g[q], d.fp16_scale);
+  }
 }
 
 // Launch modes of the fused step:
