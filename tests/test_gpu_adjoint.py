@@ -103,6 +103,42 @@ def test_direct_launches_equal_graphs():
     assert np.array_equal(ga, gb)
 
 
+def test_full_size_gradient_matches_central_differences():
+    """The 96^3 workload at full size, as the benchmark runs it (one 2000-step
+    period, checkpoints every 100 steps, default launch shape): dJ/dA and
+    dJ/dk of the adjoint against central differences of the GPU forward run
+    at a 1 % step.  The displacement is, to leading order, bilinear in the two
+    amplitudes, so the difference in A carries no truncation error (measured
+    1e-5); in k it is O(h^2): 7e-4 measured at a 2 % step, so ~2e-4 at 1 %.
+    The two FP32 forward runs of a difference agree to ~1e-5 of J, i.e. a
+    few 1e-4 of the differenced J; the adjoint's own FP32 rounding over a
+    period is ~1e-4 (reduced case).  Bar: 1e-3."""
+    case = workloads.adjoint_case(reduced=False)
+    T, K = case["steps"], case["checkpoint"]
+    sw = case["swimmers"][0]
+    theta = np.array([sw["A"], sw["B"], sw["alpha"], sw["k"][0]], dtype=np.float64)
+    lat = lbmib.from_workload(case)
+    J, g = lat.adjoint(T, checkpoint=K)
+
+    def displacement(th):
+        h = lbmib.from_workload(case)
+        h.set_swimmer_params(0, *th)
+        x0 = h.swimmer_centres()[0, 0]
+        h.step(T)
+        return h.swimmer_centres()[0, 0] - x0
+
+    assert abs(displacement(theta) - J) <= 1e-12
+    for i in (0, 3):
+        d = 0.01 * theta[i]
+        tp, tm = theta.copy(), theta.copy()
+        tp[i] += d
+        tm[i] -= d
+        fd = (displacement(tp) - displacement(tm)) / (2.0 * d)
+        print(f"parameter {i}: adjoint {g[i]:.8e} central difference {fd:.8e} "
+              f"rel {abs(g[i] - fd) / abs(fd):.2e}", flush=True)
+        assert abs(g[i] - fd) <= 1e-3 * abs(fd)
+
+
 def test_state_after_adjoint():
     """Without rewind the handle ends exactly where lbm_step(T) takes it;
     with rewind it is back at its entry state."""

@@ -7,6 +7,7 @@ rel-L2 <= 1e-5, marker positions within 1e-10 lattice units per step."""
 import numpy as np
 import pytest
 
+import bench
 from paper_2202_12147_amd import lbmib, workloads as wl
 from tests.helpers import oracle_from, rel_l2
 
@@ -48,6 +49,7 @@ def test_ensemble_parity_sampled_boxes():
     # drawn by seed are compared with the oracle
     ens = wl.ensemble(seed=0)
     batch = lbmib.batch_from_ensemble(ens)
+    batch.set_stream_collide_launch(*bench.BATCH_LAUNCH)
     steps = 200
     batch.step(steps)
     batch.sync()

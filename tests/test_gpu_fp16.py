@@ -15,6 +15,7 @@ import math
 import numpy as np
 import pytest
 
+import bench
 from oracle import orc
 from paper_2202_12147_amd import lbmib, workloads as wl
 from tests.helpers import oracle_from, rel_l2
@@ -88,6 +89,7 @@ def test_pair_storage_forms_vs_oracle(arrangement):
     res = {}
     for name, st, S in (("fp32", lbmib.FP32_SHIFTED, 1.0), ("fp16", lbmib.FP16_SHIFTED, S27)):
         lat = lbmib.from_workload(case, storage=st, fp16_scale=S)
+        lat.set_stream_collide_launch(*bench.MAIN_LAUNCH)
         lat.step(steps)
         d = lat.swimmer_centres() - X0
         res[name] = (rel_l2(lat.velocity(), o.velocity()), np.abs(d - d_o).max() / np.abs(d_o).max())
