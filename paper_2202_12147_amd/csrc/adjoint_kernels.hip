@@ -431,7 +431,19 @@ __global__ __launch_bounds__(kBlock) void k_adj_tangent(Dev d, Adj a) {
         s[2] = f.z;
         const double* c = d.bstate[b].c;
         const D3 cc = {{c[0], 0}, {c[1], 0}, {c[2], 0}};
-        const D3 pb = p[(corner + 1) % 3] - cc, pc = p[(corner + 2) % 3] - cc;
+        // the other two corners in counter-clockwise order, selected with
+        // constant indices (a computed index would put p in scratch memory)
+        D3 pb, pc;
+        if (corner == 0) {
+          pb = p[1] - cc;
+          pc = p[2] - cc;
+        } else if (corner == 1) {
+          pb = p[2] - cc;
+          pc = p[0] - cc;
+        } else {
+          pb = p[0] - cc;
+          pc = p[1] - cc;
+        }
         const D3 g = cross(pb, pc);
         s[3] = g.x.v * (1.0 / 6.0);
         s[4] = g.y.v * (1.0 / 6.0);
