@@ -102,7 +102,7 @@ struct BeadState {
   double V;             // enclosed volume
   int lo[3], hi[3];     // region: nodes [lo, hi] (unwrapped) within the kernel
                         // support of some marker
-  int tlo[3], tcnt[3];  // region in tiles: first tile (unwrapped), count
+  int tlo[3], tcnt[3];  // region in tiles: first tile (in the box), count (periodic)
 };
 
 // Everything a kernel needs, passed by value.

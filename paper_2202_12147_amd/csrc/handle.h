@@ -76,7 +76,7 @@ struct lbm_handle {
   int* d_block_box = nullptr;     // 256-node block -> box
   int* d_sc_block_box = nullptr;  // stream-collide block -> box (sized for block 128)
   int* d_sc_box_block0 = nullptr; // first stream-collide block of each box
-  int64_t sc_table_cap = 0;
+  int64_t sc_table_cap = 0;       // stream-collide blocks at block 128: sum over boxes of ceil(n / 128)
   int64_t* d_step = nullptr;
   double* d_pos = nullptr;
   float *d_U = nullptr, *d_fm = nullptr;

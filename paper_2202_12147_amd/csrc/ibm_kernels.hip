@@ -48,7 +48,6 @@ constexpr int kSpreadBlockWide = 512;
 constexpr int kWideBeads = 32;  // at most this many beads: wide workgroups
 constexpr int kInterpBlock = 256;
 
-__device__ inline int floor_div(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
 __device__ inline int pmod(int a, int b) {
   int r = a % b;
   return r < 0 ? r + b : r;
@@ -203,14 +202,27 @@ __global__ __launch_bounds__(BS) void k_bead_stats(Dev d, int mark_offset) {
     for (int k = 0; k < NV; ++k) t[k] = part[0][k];
     BeadState& st = d.bstate[b];
     const int T[3] = {Bx.tx, Bx.ty, Bx.tz};
+    const int N[3] = {Bx.nx, Bx.ny, Bx.nz};
     const int reserved[3] = {Bd.tiles_x, Bd.tiles_y, Bd.tiles_z};
     for (int a = 0; a < 3; ++a) st.c[a] = t[a] / Bd.nv;
     st.V = t[9] / 6.0;
     for (int a = 0; a < 3; ++a) {
       st.lo[a] = stencil_base<NW>(t[3 + a]);
       st.hi[a] = stencil_base<NW>(t[6 + a]) + NW - 1;
-      int t0 = floor_div(st.lo[a], kTile);
-      int cnt = floor_div(st.hi[a], kTile) - t0 + 1;
+      // Tiles from the wrapped first node, counted on in periodic tile order
+      // (tile T follows tile T - 1): node lo + j lies in tile
+      // (u / N) T + (u mod N) / kTile (mod T), u = (lo mod N) + j, which rises
+      // by at most one per node, so the region's nodes fill the tile run
+      // [t0, t0 + cnt) also on an edge that is not a whole number of tiles.
+      // A region shorter than the edge wraps at most once.
+      const int lw = pmod(st.lo[a], N[a]);
+      const int hw = lw + (st.hi[a] - st.lo[a]);
+      int t0 = lw / kTile;
+      int cnt = T[a];
+      if (hw < lw)
+        cnt = 0;  // no region (non-finite positions)
+      else if (hw - lw + 1 < N[a])
+        cnt = (hw < N[a] ? hw / kTile : T[a] + (hw - N[a]) / kTile) - t0 + 1;
       if (cnt >= T[a]) {
         t0 = 0;
         cnt = T[a];

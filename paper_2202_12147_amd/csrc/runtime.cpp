@@ -111,9 +111,12 @@ float lattice_weight(int q) { return q == 0 ? 1.0f / 3.0f : (q < 7 ? 1.0f / 18.0
 
 // Candidate tiles reserved per axis for a bead: the node span of its stencils
 // with 25% room for deformation, in tiles, for any alignment.
-int reserved_tiles(double radius, int width, int T) {
+int reserved_tiles(double radius, int width, int n, int T) {
   const int span = (int)std::floor(2.0 * radius * 1.25) + width + 2;
-  return std::min(T, (span + kTile - 2) / kTile + 1);
+  // an edge that is not a whole number of tiles ends in a short tile, which a
+  // run of nodes across it may touch on top of the whole tiles
+  const int shorter = n % kTile ? 1 : 0;
+  return std::min(T, (span + kTile - 2) / kTile + 1 + shorter);
 }
 
 // Host layout of population deviations: box after box, each [19][n_box];
@@ -283,8 +286,10 @@ int upload(lbm_handle* h) {
   h->d_lane_v = h->alloc<int>(lane_v.size(), rc);
   h->d_spread_bead = h->alloc<int>(spread_bead.size(), rc);
   h->d_centres = h->alloc<double>(3 * h->beads.size(), rc);
-  // near-block buffers, sized for the smallest stream-collide block (128)
-  const int64_t nsc_max = (h->nodes + 127) / 128;
+  // near-block buffers, sized for the smallest stream-collide block (128):
+  // every box starts a new block, so the bound is the sum over the boxes of
+  // ceil(n / 128), not ceil(nodes / 128)
+  const int64_t nsc_max = h->sc_table_cap;
   h->d_near = h->alloc<int>(kNearSlots * (size_t)nsc_max, rc);
   h->d_near_list = h->alloc<int>(2 * (size_t)nsc_max, rc);
   h->d_near_count = h->alloc<int>(2, rc);
@@ -745,9 +750,9 @@ int lbm_batch_swimmer_add(lbm_handle* h, int32_t box, const lbm_bead_desc beads[
     b.box = box;
     b.swimmer = sw;
     b.slot = k;
-    b.tiles_x = reserved_tiles(bd.radius, h->width, B.tx);
-    b.tiles_y = reserved_tiles(bd.radius, h->width, B.ty);
-    b.tiles_z = reserved_tiles(bd.radius, h->width, B.tz);
+    b.tiles_x = reserved_tiles(bd.radius, h->width, B.nx, B.tx);
+    b.tiles_y = reserved_tiles(bd.radius, h->width, B.ny, B.ty);
+    b.tiles_z = reserved_tiles(bd.radius, h->width, B.nz, B.tz);
     b.ks = (float)bd.kappa_s;
     b.C = (float)bd.C;
     b.kt = (float)(2.0 * bd.kappa_b / std::sqrt(3.0));
@@ -1201,7 +1206,7 @@ void snapshot_parts(lbm_handle* h, Snapshot& S) {
              {h->u, sizeof(float) * 3 * h->pstride}, {h->stamp, sizeof(int) * h->ntiles},
              {h->d_step, sizeof(int64_t)}, {h->d_overflow, sizeof(int)}};
   if (h->uploaded && h->nm > 0) {
-    const size_t nsc_max = (size_t)((h->nodes + 127) / 128);
+    const size_t nsc_max = (size_t)h->sc_table_cap;
     S.parts.push_back({h->d_pos, sizeof(double) * 3 * h->nm});
     S.parts.push_back({h->d_U, sizeof(float) * 3 * h->nm});
     S.parts.push_back({h->d_fm, sizeof(float) * 3 * h->nm});

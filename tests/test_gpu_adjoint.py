@@ -211,11 +211,15 @@ def test_adjoint_rejects_unsupported():
     assert not math.isnan(lat.adjoint(2)[0])
 
 
-def test_adjoint_across_periodic_seams():
-    """Swimmer straddling the x and y seams of the 24^3 box: the transposed
-    spreading and interpolation wrap like the forward ones."""
+@pytest.mark.parametrize("shape", [(24, 24, 24), (25, 22, 23)])
+def test_adjoint_across_periodic_seams(shape):
+    """Swimmer straddling the x and y seams: the transposed spreading and
+    interpolation wrap like the forward ones.  The 25x22x23 box has no edge
+    that is a whole number of 8-node tiles."""
     case = _case()
-    case["swimmers"] = [workloads.swimmer((23.5, 0.4, 12.0), 7.0, A=1e-3, T=2000.0, alpha=math.pi / 3)]
+    case["shape"] = shape
+    mid = (shape[0] - 0.5, 0.4, shape[2] / 2)
+    case["swimmers"] = [workloads.swimmer(mid, 7.0, A=1e-3, T=2000.0, alpha=math.pi / 3)]
     lat = lbmib.from_workload(case)
     J, g = lat.adjoint(40, checkpoint=16)
     Jo, go = oracle_adjoint.displacement_gradient(case, 40, checkpoint_every=0)

@@ -156,3 +156,26 @@ def test_swimmer_across_periodic_seams(width):
     assert du < 1e-5
     assert dr < POS_PER_STEP * steps
     np.testing.assert_allclose(lat.swimmer_centres(), o.swimmer_centres(), rtol=0, atol=POS_PER_STEP * steps)
+
+
+@pytest.mark.parametrize("offset", [(0, 0, 0), (2, -1, 3)])
+def test_swimmer_across_seams_of_ragged_box(offset):
+    """Edges 39, 34 and 37 are not whole numbers of 8-node tiles, so every axis
+    ends in a short tile.  The middle bead straddles the x and y seams and the
+    last bead lies past the x seam; with `offset` the swimmer is moved by whole
+    box lengths, so its (unwrapped) marker coordinates lie far outside the box.
+    Every bead region must still map onto the tiles holding its nodes.  Same
+    bars as the centred case."""
+    case = wl.small_case()
+    case["shape"] = (39, 34, 37)
+    shift = np.asarray(offset, float) * np.asarray(case["shape"], float)
+    case["swimmers"] = [wl.swimmer(tuple(np.array((38.4, 33.5, 18.2)) + shift), 10.0, A=1e-3, T=500.0)]
+    steps = 150
+    print("ragged seam case", offset, steps, flush=True)
+    o, lat = _run_pair(case, steps)
+    du = rel_l2(lat.velocity(), o.velocity())
+    dr = np.abs(lat.markers() - o.markers()).max()
+    print("rel-L2 u", du, "max |dr|", dr, flush=True)
+    assert du < 1e-5
+    assert dr < POS_PER_STEP * steps
+    np.testing.assert_allclose(lat.swimmer_centres(), o.swimmer_centres(), rtol=0, atol=POS_PER_STEP * steps)
