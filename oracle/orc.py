@@ -249,6 +249,22 @@ class Oracle:
         self.lib.orc_get_velocity(self.h, u)
         return u
 
+    def average_velocity(self, steps, every=1):
+        """Time-averaged fluid velocity, as in the period-averaged flow fields
+        of the paper's results (Sec. 3, Figs. 3, 6 and 9, one swimming period):
+        advance `steps` steps and return the mean, over the sampled steps, of
+        the physical velocity u = (sum f c + F/2) / rho each of them computes
+        (Sec. 2.1), with the number of samples.  The first of the steps is
+        sampled and then every `every`-th one."""
+        acc = np.zeros(self._fshape(3))
+        count = 0
+        for k in range(int(steps)):
+            self.step(1)
+            if k % int(every) == 0:
+                acc += self.velocity()
+                count += 1
+        return (acc / count if count else acc), count
+
     def density(self):
         nx, ny, nz = self.shape
         r = np.zeros((nz, ny, nx))
