@@ -124,6 +124,37 @@ def fp16_section(lbmib, wl, case, steps, warmup, gmax):
                                         "plain_rel_diff": abs(disp["fp32_plain"] - disp["fp32"]) / abs(disp["fp32"])}}
 
 
+def average_section(lbmib, lat, nodes, steps=2000):
+    """Cost of the time-averaged velocity field on the same handle: step
+    time with every step sampled and with every tenth, and the full-grid
+    stream-collide kernel of a sampled step, whose algorithmic traffic is
+    152 + 48 bytes per node (the FP64 sums of u are read and written)."""
+    res = {}
+    for every in (1, 10):
+        lat.average_begin(every)
+        lat.step(64)
+        lat.sync()
+        t0 = time.perf_counter()
+        lat.step(steps)
+        lat.sync()
+        res[f"every_{every}_ms_per_step"] = round((time.perf_counter() - t0) / steps * 1e3, 5)
+    lat.average_begin(1)
+    lat.set_stream_collide_launch(*KERNEL_LAUNCH)
+    lat.step(20)
+    lat.set_kernel_timing(True)
+    lat.step(steps)
+    kms, n = lat.kernel_time()
+    lat.set_kernel_timing(False)
+    lat.sync()
+    lat.average_begin(0)
+    lat.set_stream_collide_launch(*MAIN_LAUNCH)
+    avg_ms = kms / max(n, 1)
+    nbytes = lat.bytes_per_step + 48 * nodes
+    res.update(sampled_kernel_ms=round(avg_ms, 5), bytes_per_sampled_launch=nbytes,
+               sampled_kernel_gbs=round(nbytes / (avg_ms * 1e-3) / 1e9, 1))
+    return res
+
+
 def batch_section(lbmib, wl, steps=5000, warmup=200, seed=0):
     """The 64-box ensemble (edges from {48,64,80,96} per axis, one swimmer
     each) advanced together: the launch shape the autotuner picked for it, then `steps` timed
@@ -279,6 +310,7 @@ def main():
     if not args.main_only:
         import numpy as np
         gmax = float(np.abs(lat.populations()).max())
+        out["average"] = average_section(lbmib, lat, nodes)
         out["fp16"] = fp16_section(lbmib, wl, case, args.steps, args.warmup, gmax)
         del lat
         out["batch"] = batch_section(lbmib, wl)

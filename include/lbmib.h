@@ -169,6 +169,26 @@ int lbm_get_velocity(lbm_handle* h, float* dst, int on_device);
 /* Density rho_n of the last completed step, dst[nz][ny][nx] float32. */
 int lbm_get_density(lbm_handle* h, float* dst, int on_device);
 
+/* Time-averaged fluid velocity, the quantity of the period-averaged flow
+ * fields in the results (Sec. 3, Figs. 3, 6 and 9: the average over one
+ * swimming period).  lbm_average_begin(h, every), every >= 1, starts a new
+ * average: from the next step on, that step and every every-th step after it
+ * add their physical velocity u (as lbm_get_velocity) to per-node float64
+ * sums held on the device (24 bytes per node, allocated on first use, freed
+ * by lbm_destroy); every = 1 samples every step.  The stream-collide launches
+ * add u as they compute it: a sampled step moves 48 more bytes per node.
+ * every = 0 stops the average.  lbm_load stops it (the sums and the
+ * sampling schedule are not part of a checkpoint), lbm_autotune keeps its
+ * trial steps out of it, and lbm_adjoint fails with LBM_ESTATE while one
+ * runs.  Errors: LBM_EINVAL (every < 0), LBM_ENOMEM. */
+int lbm_average_begin(lbm_handle* h, int32_t every);
+/* Mean of the sampled velocities of box `box` (0 for a single box), dst
+ * [3][nz][ny][nx] float32, device (on_device = 1) or host memory; zero when
+ * no step has been sampled yet.  *samples (if non-NULL) receives the number
+ * of steps averaged.  Synchronous.  LBM_ESTATE when no average is running,
+ * LBM_EINVAL for a box out of range. */
+int lbm_get_average_velocity(lbm_handle* h, int32_t box, float* dst, int on_device, int64_t* samples);
+
 /* out[0] = sum over nodes and populations of f*, out[1..3] = sum f* c, of the
  * current post-collision state, reduced in float64 on the device.
  * LBM_ENONFINITE if any sum is NaN or Inf. */

@@ -168,6 +168,11 @@ struct Dev {
   // (rho, u) of every node, written by the moment-recording stream-collide
   // variant only (segment recompute of the adjoint)
   float4* mom;
+  // time average of the fluid velocity (optional): FP64 sums uavg[3][node]
+  // of the u of steps avg_t0, avg_t0 + avg_every, ...; null when off
+  double* uavg;
+  int64_t avg_t0;
+  int avg_every;
   // optional out-of-place variants (adjoint segment recompute): advection
   // writes r + U to pos_next instead of pos, and bead statistics take the
   // previous centres from bstate_prev instead of bstate
@@ -187,6 +192,9 @@ void launch_stream_collide_mom(const Dev& d, int mode, int nblocks, hipStream_t 
 void launch_tick(const Dev& d, int count, hipStream_t s);
 void launch_velocity(const Dev& d, int storage, int nblocks, float* u_out, float* rho_out,
                      hipStream_t s);
+// Mean velocity from the sums d.uavg over `count` samples (zero when count is
+// 0), written box after box as [box][3][n_box] like launch_velocity.
+void launch_average_out(const Dev& d, int nblocks, int64_t count, float* u_out, hipStream_t s);
 void launch_conserved(const Dev& d, int storage, int box, double* partial, int nparts, double* out,
                       hipStream_t s);
 void launch_bead_stats(const Dev& d, int mark_offset, hipStream_t s);

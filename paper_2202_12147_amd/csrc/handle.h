@@ -71,6 +71,7 @@ struct lbm_handle {
   // device buffers
   void* pop[2] = {nullptr, nullptr};
   float *F = nullptr, *u = nullptr, *uout = nullptr;
+  double* avg_sums = nullptr;     // time-average sums [3][pstride] (allocated on first use)
   int* stamp = nullptr;
   Box* d_boxes = nullptr;
   int* d_block_box = nullptr;     // 256-node block -> box

@@ -129,17 +129,23 @@ __device__ inline Moments moments(const float* g) {
 // BGK collision of one direction pair (+c, -c) with weight w.
 //   e    = c . u_eq, the equilibrium velocity projection
 //   cu,cf = c . u and c . F (Guo source), uf = u . F
+// Every sum of two products is written as an explicit fmaf: left to the
+// compiler, which product is fused can differ between template instances of
+// the caller and change the last bit, and the launch variants of the step
+// must agree bit for bit.
 __device__ inline void collide_pair(float& gp, float& gm, float w, float om, float drho, float rho,
                                     float usq15, float e, float src_a, float cu, float cf,
                                     float uf) {
-  const float sym = w * (drho + rho * (4.5f * e * e - usq15));
-  const float asym = w * rho * 3.0f * e;
+  const float sym = w * (drho + rho * fmaf(4.5f * e, e, -usq15));
+  const float wr3 = w * rho * 3.0f;
+  const float eqp = fmaf(wr3, e, sym), eqm = fmaf(-wr3, e, sym);
   // Guo source: src_a (1 - om/2) w [3 (c - u).F + 9 (c.u)(c.F)], zero for Shan-Chen
-  const float s_sym = src_a * w * (-3.0f * uf + 9.0f * cu * cf);
-  const float s_asym = src_a * w * 3.0f * cf;
-  const float eqp = sym + asym, eqm = sym - asym;
-  gp = gp + om * (eqp - gp) + (s_sym + s_asym);
-  gm = gm + om * (eqm - gm) + (s_sym - s_asym);
+  const float sw = src_a * w;
+  const float s_sym = sw * fmaf(9.0f * cu, cf, -3.0f * uf);
+  const float sw3 = sw * 3.0f;
+  const float sp = fmaf(sw3, cf, s_sym), sm = fmaf(-sw3, cf, s_sym);
+  gp = gp + om * (eqp - gp) + sp;
+  gm = gm + om * (eqm - gm) + sm;
 }
 
 // Workgroup -> logical block.  Workgroups are handed to the 8 XCDs round
@@ -154,16 +160,25 @@ __device__ inline int logical_block(int remap, int nblocks) {
 
 // One node of the fused step: pull, moments, forcing, BGK collision, store.
 // `forced`: read F and write u at this node (its tile is active this step).
+// `avg`: add u to the node's time-average sums (a sampled step).
 // MOM: also record (rho, u) of the node in d.mom.
 template <int ST, bool MOM = false>
 __device__ inline void sc_node(const Dev& d, const Box& B, int x, int y, int z, int64_t base,
-                               int64_t n, bool forced) {
+                               int64_t n, bool forced, bool avg) {
   using IO = PopIO<ST>;
   using T = typename IO::T;
   const Nbr o = neighbours(x, y, z, B.nx, B.ny, B.nz);
   const T* __restrict__ src = static_cast<const T*>(d.pop[n & 1]);
   T* __restrict__ dst = static_cast<T*>(d.pop[(n + 1) & 1]);
   const int64_t ps = d.pstride;
+  // a sampled step loads the node's sums with the pulls, so that their
+  // latency overlaps (the persistent bulk launch runs two waves per SIMD)
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  if (avg) {
+    a0 = d.uavg[base];
+    a1 = d.uavg[ps + base];
+    a2 = d.uavg[2 * ps + base];
+  }
   float g[kQ];
   pull<ST>(src, base, o, d.fp16_inv, g);
   const Moments m = moments(g);
@@ -195,8 +210,8 @@ __device__ inline void sc_node(const Dev& d, const Box& B, int x, int y, int z, 
     src_a = 0.0f;
   }
   const float om = B.omega;
-  const float usq15 = 1.5f * (ex * ex + ey * ey + ez * ez);
-  const float uf = ux * Fx + uy * Fy + uz * Fz;
+  const float usq15 = 1.5f * fmaf(ez, ez, fmaf(ey, ey, ex * ex));
+  const float uf = fmaf(uz, Fz, fmaf(uy, Fy, ux * Fx));
   // rest population
   {
     const float eq0 = kW0 * (m.drho - m.rho * usq15);
@@ -221,6 +236,17 @@ __device__ inline void sc_node(const Dev& d, const Box& B, int x, int y, int z, 
 #pragma unroll
     for (int q = 0; q < kQ; ++q) IO::st(bq + q * kPopBlock, q, g[q], d.fp16_scale);
   }
+  if (avg) {
+    double* __restrict__ acc = d.uavg;
+    acc[base] = a0 + (double)ux;
+    acc[ps + base] = a1 + (double)uy;
+    acc[2 * ps + base] = a2 + (double)uz;
+  }
+}
+
+// Whether step n adds to the time-average sums (uniform over a launch).
+__device__ inline bool avg_sampled(const Dev& d, int64_t n) {
+  return d.uavg != nullptr && n >= d.avg_t0 && (n - d.avg_t0) % d.avg_every == 0;
 }
 
 // Launch modes of the fused step:
@@ -235,7 +261,7 @@ __device__ inline void sc_node(const Dev& d, const Box& B, int x, int y, int z, 
 constexpr int kScAll = kLaunchAll, kScBulk = kLaunchBulk, kScActive = kLaunchActive;
 
 template <int ST, int BS, bool MOM = false>
-__device__ inline void sc_block(const Dev& d, int blk, int64_t n, bool bulk) {
+__device__ inline void sc_block(const Dev& d, int blk, int64_t n, bool bulk, bool avg) {
   const int b = d.nboxes == 1 ? 0 : d.sc_block_box[blk];
   const Box B = d.boxes[b];
   const int first = d.nboxes == 1 ? 0 : d.sc_box_block0[b];
@@ -252,36 +278,39 @@ __device__ inline void sc_block(const Dev& d, int blk, int64_t n, bool bulk) {
     const int tile = B.tile0 + (x / kTile) + B.tx * ((y / kTile) + B.ty * (z / kTile));
     forced = d.stamp[tile] == (int)n;
   }
-  sc_node<ST, MOM>(d, B, x, y, z, B.node0 + id, n, forced);
+  sc_node<ST, MOM>(d, B, x, y, z, B.node0 + id, n, forced, avg);
 }
 
-template <int ST, int BS, int MODE>
+// AVG: the variant launched while a time average of u runs (the sampling
+// test and the sums); without it the averaging code is compiled out.
+template <int ST, int BS, int MODE, bool AVG>
 __global__ __launch_bounds__(BS) void k_stream_collide(Dev d, int remap, int nblocks, int resident) {
   const int64_t n = *d.step + d.sub;
   const int64_t pn = n - 1;  // the step whose bead statistics marked the near blocks
   const int pp = (int)(pn & 1), pf = near_slot(pn);
+  const bool avg = AVG && avg_sampled(d, n);
   if constexpr (MODE == kScActive) {
     const int cnt = min(d.near_count[pp], d.max_near);
-    if ((int)blockIdx.x < cnt) sc_block<ST, BS>(d, d.near_list[pp * d.max_near + blockIdx.x], n, false);
+    if ((int)blockIdx.x < cnt) sc_block<ST, BS>(d, d.near_list[pp * d.max_near + blockIdx.x], n, false, avg);
   } else if constexpr (MODE == kScBulk) {
     if (resident && remap) {
       const int per = (nblocks + 7) / 8;  // logical blocks per XCD
       const int xcd = blockIdx.x % 8, g8 = (int)gridDim.x / 8;
       for (int j = blockIdx.x / 8; j < per; j += g8) {
         const int blk = xcd * per + j;
-        if (blk < nblocks && d.near[pf * d.nsc + blk] != (int)pn) sc_block<ST, BS>(d, blk, n, true);
+        if (blk < nblocks && d.near[pf * d.nsc + blk] != (int)pn) sc_block<ST, BS>(d, blk, n, true, avg);
       }
     } else if (resident) {
       // grid-stride: consecutive blocks go to consecutive workgroups (round robin over the XCDs)
       for (int blk = blockIdx.x; blk < nblocks; blk += (int)gridDim.x)
-        if (d.near[pf * d.nsc + blk] != (int)pn) sc_block<ST, BS>(d, blk, n, true);
+        if (d.near[pf * d.nsc + blk] != (int)pn) sc_block<ST, BS>(d, blk, n, true, avg);
     } else {
       const int blk = logical_block(remap, nblocks);
-      if (blk < nblocks && d.near[pf * d.nsc + blk] != (int)pn) sc_block<ST, BS>(d, blk, n, true);
+      if (blk < nblocks && d.near[pf * d.nsc + blk] != (int)pn) sc_block<ST, BS>(d, blk, n, true, avg);
     }
   } else {
     const int blk = logical_block(remap, nblocks);
-    if (blk < nblocks) sc_block<ST, BS>(d, blk, n, false);
+    if (blk < nblocks) sc_block<ST, BS>(d, blk, n, false, avg);
   }
 }
 
@@ -294,12 +323,13 @@ __global__ __launch_bounds__(kScBlock) void k_stream_collide_mom(Dev d, int nblo
   const int pp = (int)(pn & 1), pf = near_slot(pn);
   if constexpr (MODE == kScActive) {
     const int cnt = min(d.near_count[pp], d.max_near);
-    if ((int)blockIdx.x < cnt) sc_block<kFp32, kScBlock, true>(d, d.near_list[pp * d.max_near + blockIdx.x], n, false);
+    if ((int)blockIdx.x < cnt)
+      sc_block<kFp32, kScBlock, true>(d, d.near_list[pp * d.max_near + blockIdx.x], n, false, false);
   } else if constexpr (MODE == kScBulk) {
     const int blk = blockIdx.x;
-    if (blk < nblocks && d.near[pf * d.nsc + blk] != (int)pn) sc_block<kFp32, kScBlock, true>(d, blk, n, true);
+    if (blk < nblocks && d.near[pf * d.nsc + blk] != (int)pn) sc_block<kFp32, kScBlock, true>(d, blk, n, true, false);
   } else {
-    if ((int)blockIdx.x < nblocks) sc_block<kFp32, kScBlock, true>(d, blockIdx.x, n, false);
+    if ((int)blockIdx.x < nblocks) sc_block<kFp32, kScBlock, true>(d, blockIdx.x, n, false, false);
   }
 }
 
@@ -357,6 +387,21 @@ __global__ __launch_bounds__(kScBlock) void k_velocity(Dev d, float* __restrict_
     uo[2 * nb + ob] = (m.jz + 0.5f * Fz) * ir;
   }
   if (ro) ro[orho] = m.rho;
+}
+
+// Time-average of u: the FP64 sums over `count` sampled steps divided by the
+// count (zero without samples), box after box as [box][3][n_box].
+__global__ __launch_bounds__(kScBlock) void k_average_out(Dev d, int64_t count, float* __restrict__ uo) {
+  const int blk = blockIdx.x;
+  const int b = d.nboxes == 1 ? 0 : d.block_box[blk];
+  const Box B = d.boxes[b];
+  const int id = (blk - B.block0) * kScBlock + (int)threadIdx.x;
+  if (id >= B.n) return;
+  const int64_t ob = 3 * B.node0 + id, nb = B.n, base = B.node0 + id, ps = d.pstride;
+  const double inv = count > 0 ? 1.0 / (double)count : 0.0;
+  uo[ob] = (float)(d.uavg[base] * inv);
+  uo[nb + ob] = (float)(d.uavg[ps + base] * inv);
+  uo[2 * nb + ob] = (float)(d.uavg[2 * ps + base] * inv);
 }
 
 // Block sum of 4 doubles through wavefront shuffles, result in thread 0.
@@ -447,7 +492,7 @@ static void launch_k(K kernel, int grid, int block, hipStream_t s, hipEvent_t ev
     hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), 0, s, d, remap, nblocks, resident);
 }
 
-template <int ST, int MODE>
+template <int ST, int MODE, bool AVG>
 static void launch_sc_mode(const Dev& d, int block, int nblocks, int remap, int resident, int ncu,
                            hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   int grid = remap ? (nblocks + 7) / 8 * 8 : nblocks;
@@ -456,22 +501,31 @@ static void launch_sc_mode(const Dev& d, int block, int nblocks, int remap, int 
     grid = remap ? std::min(grid, ncu * resident) / 8 * 8 : std::min(grid, ncu * resident);
   if (MODE != kScBulk) resident = 0;
   if (block == 128)
-    launch_k(k_stream_collide<ST, 128, MODE>, grid, 128, s, ev0, ev1, d, remap, nblocks, resident);
+    launch_k(k_stream_collide<ST, 128, MODE, AVG>, grid, 128, s, ev0, ev1, d, remap, nblocks, resident);
   else if (block == 512)
-    launch_k(k_stream_collide<ST, 512, MODE>, grid, 512, s, ev0, ev1, d, remap, nblocks, resident);
+    launch_k(k_stream_collide<ST, 512, MODE, AVG>, grid, 512, s, ev0, ev1, d, remap, nblocks, resident);
   else
-    launch_k(k_stream_collide<ST, 256, MODE>, grid, 256, s, ev0, ev1, d, remap, nblocks, resident);
+    launch_k(k_stream_collide<ST, 256, MODE, AVG>, grid, 256, s, ev0, ev1, d, remap, nblocks, resident);
+}
+
+template <int ST, bool AVG>
+static void launch_sc_avg(const Dev& d, int mode, int block, int nblocks, int remap, int resident,
+                          int ncu, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+  if (mode == kScBulk)
+    launch_sc_mode<ST, kScBulk, AVG>(d, block, nblocks, remap, resident, ncu, s, ev0, ev1);
+  else if (mode == kScActive)
+    launch_sc_mode<ST, kScActive, AVG>(d, block, nblocks, remap, resident, ncu, s, ev0, ev1);
+  else
+    launch_sc_mode<ST, kScAll, AVG>(d, block, nblocks, remap, resident, ncu, s, ev0, ev1);
 }
 
 template <int ST>
 static void launch_sc_st(const Dev& d, int mode, int block, int nblocks, int remap, int resident,
                          int ncu, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
-  if (mode == kScBulk)
-    launch_sc_mode<ST, kScBulk>(d, block, nblocks, remap, resident, ncu, s, ev0, ev1);
-  else if (mode == kScActive)
-    launch_sc_mode<ST, kScActive>(d, block, nblocks, remap, resident, ncu, s, ev0, ev1);
+  if (d.uavg)
+    launch_sc_avg<ST, true>(d, mode, block, nblocks, remap, resident, ncu, s, ev0, ev1);
   else
-    launch_sc_mode<ST, kScAll>(d, block, nblocks, remap, resident, ncu, s, ev0, ev1);
+    launch_sc_avg<ST, false>(d, mode, block, nblocks, remap, resident, ncu, s, ev0, ev1);
 }
 
 void launch_stream_collide(const Dev& d, int storage, int mode, int block, int nblocks, int remap,
@@ -505,6 +559,10 @@ void launch_velocity(const Dev& d, int storage, int nblocks, float* u_out, float
     hipLaunchKernelGGL(k_velocity<kFp32Plain>, dim3(nblocks), dim3(kScBlock), 0, s, d, u_out, rho_out);
   else
     hipLaunchKernelGGL(k_velocity<kFp32>, dim3(nblocks), dim3(kScBlock), 0, s, d, u_out, rho_out);
+}
+
+void launch_average_out(const Dev& d, int nblocks, int64_t count, float* u_out, hipStream_t s) {
+  hipLaunchKernelGGL(k_average_out, dim3(nblocks), dim3(kScBlock), 0, s, d, count, u_out);
 }
 
 void launch_conserved(const Dev& d, int storage, int box, double* partial, int nparts, double* out,

@@ -505,6 +505,21 @@ void harvest_timing(lbm_handle* h) {
   h->ev_used = 0;
 }
 
+// Point the stream-collide launches at the time-average state.  Captured
+// graphs hold the previous kernel arguments, so they are dropped and
+// recaptured on the next step.
+int set_average(lbm_handle* h, double* sums, int64_t t0, int every) {
+  int rc = h->hip(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+  if (rc) return rc;
+  h->dev.uavg = sums;
+  h->dev.avg_t0 = t0;
+  h->dev.avg_every = every;
+  if (h->g_chunk) (void)hipGraphExecDestroy(h->g_chunk);
+  if (h->g_one) (void)hipGraphExecDestroy(h->g_one);
+  h->g_chunk = h->g_one = nullptr;
+  return LBM_OK;
+}
+
 int check_overflow(lbm_handle* h) {
   if (!h->uploaded || h->swimmers.empty()) return LBM_OK;
   int ov = 0;
@@ -1124,7 +1139,58 @@ int checkpoint(lbm_handle* h, const char* path, bool save) {
 }  // namespace
 
 int lbm_save(lbm_handle* h, const char* path) { return checkpoint(h, path, true); }
-int lbm_load(lbm_handle* h, const char* path) { return checkpoint(h, path, false); }
+int lbm_load(lbm_handle* h, const char* path) {
+  int rc = checkpoint(h, path, false);
+  if (!rc && h->dev.uavg) rc = set_average(h, nullptr, 0, 0);  // the step count jumped
+  return rc;
+}
+
+// ---- time-averaged velocity ------------------------------------------------------------
+int lbm_average_begin(lbm_handle* h, int32_t every) {
+  if (!h || every < 0) return LBM_EINVAL;
+  if (every == 0) return set_average(h, nullptr, 0, 0);
+  int rc = LBM_OK;
+  const size_t bytes = sizeof(double) * 3 * (size_t)h->pstride;
+  if (!h->avg_sums) {
+    h->avg_sums = h->alloc<double>(3 * (size_t)h->pstride, rc);
+    if (rc) return h->fail(rc, "velocity average allocation failed");
+  }
+  rc = h->hip(hipMemsetAsync(h->avg_sums, 0, bytes, h->stream), "hipMemsetAsync");
+  if (rc) return rc;
+  return set_average(h, h->avg_sums, h->host_step, every);
+}
+
+int lbm_get_average_velocity(lbm_handle* h, int32_t box, float* dst, int on_device, int64_t* samples) {
+  if (!h || !dst) return LBM_EINVAL;
+  if (box < 0 || box >= (int)h->boxes.size()) return h->fail(LBM_EINVAL, "box index out of range");
+  if (!h->dev.uavg) return h->fail(LBM_ESTATE, "no velocity average is running (lbm_average_begin)");
+  const Box& B = h->boxes[box];
+  const int64_t span = h->host_step - h->dev.avg_t0;
+  const int64_t count = span > 0 ? (span + h->dev.avg_every - 1) / h->dev.avg_every : 0;
+  int rc = LBM_OK;
+  float* target = dst;
+  const bool direct = on_device && h->boxes.size() == 1;
+  if (!direct) {
+    if (!h->uout) {
+      h->uout = h->alloc<float>(3 * h->nodes, rc);
+      if (rc) return h->fail(rc, "velocity staging allocation failed");
+    }
+    target = h->uout;
+  }
+  launch_average_out(h->dev, h->out_blocks, count, target, h->stream);
+  rc = h->hip(hipGetLastError(), "k_average_out launch");
+  if (rc) return rc;
+  if (!direct) {
+    rc = h->hip(hipMemcpyAsync(dst, target + 3 * B.node0, sizeof(float) * 3 * B.n,
+                               on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, h->stream),
+                "hipMemcpyAsync");
+    if (rc) return rc;
+  }
+  rc = h->hip(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+  if (rc) return rc;
+  if (samples) *samples = count;
+  return LBM_OK;
+}
 
 // ---- measurement -------------------------------------------------------------------
 int lbm_set_kernel_timing(lbm_handle* h, int on) {
@@ -1295,10 +1361,18 @@ int lbm_autotune(lbm_handle* h, int32_t steps, const char* cache_path, char* rep
   for (int blk : {128, 256, 512})
     for (int remap : {0, 1})
       for (int res : residents) cands.push_back({blk, remap, res});
+  // the trial steps are rewound: keep them out of a running velocity average
+  double* const avg_sums = h->dev.uavg;
+  const int64_t avg_t0 = h->dev.avg_t0;
+  const int avg_every = h->dev.avg_every;
+  if (avg_sums && (rc = set_average(h, nullptr, 0, 0))) return rc;
   rt::Snapshot S;
   rt::snapshot_parts(h, S);
   const size_t total = rt::snapshot_bytes(S);
-  if (hipMalloc(&S.mem, total) != hipSuccess) return h->fail(LBM_ENOMEM, "tuner snapshot allocation failed");
+  if (hipMalloc(&S.mem, total) != hipSuccess) {
+    if (avg_sums) (void)set_average(h, avg_sums, avg_t0, avg_every);
+    return h->fail(LBM_ENOMEM, "tuner snapshot allocation failed");
+  }
   rc = rt::snapshot_copy(h, S, true);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (!rc) rc = h->hip(hipEventCreate(&e0), "hipEventCreate");
@@ -1336,6 +1410,7 @@ int lbm_autotune(lbm_handle* h, int32_t steps, const char* cache_path, char* rep
   int rc2 = lbm_set_stream_collide_launch(h, win.block, win.remap, win.resident);
   if (!rc2) rc2 = rt::snapshot_copy(h, S, false);
   (void)hipFree(S.mem);
+  if (!rc2 && avg_sums) rc2 = set_average(h, avg_sums, avg_t0, avg_every);
   if (!rc) rc = rc2;
   if (!rc && cache_path && best < 1e300) {
     FILE* f = fopen(cache_path, "a");

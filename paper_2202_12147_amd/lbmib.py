@@ -26,6 +26,7 @@ SYMBOLS = [
     "lbm_get_bead_centres", "lbm_get_markers", "lbm_get_marker_velocities",
     "lbm_get_marker_forces", "lbm_get_velocity",
     "lbm_get_density", "lbm_get_conserved", "lbm_set_populations", "lbm_get_populations",
+    "lbm_average_begin", "lbm_get_average_velocity",
     "lbm_save", "lbm_load", "lbm_set_kernel_timing", "lbm_kernel_time", "lbm_bytes_per_step",
     "lbm_probe_copy_bandwidth", "lbm_set_stream_collide_launch",
     "lbm_batch_create", "lbm_batch_swimmer_add", "lbm_n_boxes", "lbm_batch_get_velocity",
@@ -115,6 +116,8 @@ def load_library():
         "lbm_get_conserved": (C.c_int, [vp, dp]),
         "lbm_set_populations": (C.c_int, [vp, dp]),
         "lbm_get_populations": (C.c_int, [vp, dp]),
+        "lbm_average_begin": (C.c_int, [vp, i32]),
+        "lbm_get_average_velocity": (C.c_int, [vp, i32, fp, C.c_int, C.POINTER(i64)]),
         "lbm_save": (C.c_int, [vp, C.c_char_p]),
         "lbm_load": (C.c_int, [vp, C.c_char_p]),
         "lbm_set_kernel_timing": (C.c_int, [vp, C.c_int]),
@@ -295,6 +298,31 @@ class Lattice:
         self._check(self.lib.lbm_get_velocity(self.h, _ptr(out), 0))
         return out
 
+    def average_begin(self, every=1):
+        """Start a new time average of u over this step and every `every`-th
+        step after it (every = 0 stops it)."""
+        self._check(self.lib.lbm_average_begin(self.h, int(every)))
+
+    def average_velocity(self, box=0, device=None):
+        """(mean u of the sampled steps [3, nz, ny, nx] float32, sample
+        count): numpy on the host, or a torch tensor on ``device``."""
+        nx, ny, nz = self._box_shape(box)
+        count = C.c_int64()
+        if device is not None:
+            import torch
+            t = torch.empty((3, nz, ny, nx), dtype=torch.float32, device=device)
+            self._check(self.lib.lbm_get_average_velocity(self.h, int(box), C.c_void_p(t.data_ptr()), 1,
+                                                          C.byref(count)))
+            return t, count.value
+        out = np.zeros((3, nz, ny, nx), np.float32)
+        self._check(self.lib.lbm_get_average_velocity(self.h, int(box), _ptr(out), 0, C.byref(count)))
+        return out, count.value
+
+    def _box_shape(self, box):
+        if box != 0:
+            raise ValueError("a single-box handle has box 0 only")
+        return self.shape
+
     def density(self):
         nx, ny, nz = self.shape
         out = np.zeros((nz, ny, nx), np.float32)
@@ -413,6 +441,9 @@ class Batch(Lattice):
         self._check(self.lib.lbm_batch_swimmer_add(self.h, int(box), beads, springs, C.byref(act),
                                                    C.byref(sid)))
         return sid.value
+
+    def _box_shape(self, box):
+        return self.shapes[box]
 
     def velocity(self, box=0):
         nx, ny, nz = self.shapes[box]
