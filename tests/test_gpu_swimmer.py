@@ -88,6 +88,23 @@ def test_single_128_parity_few_steps():
     assert np.abs(lat.markers() - o.markers()).max() < POS_PER_STEP * 40
 
 
+def test_paper_box_parity_few_steps():
+    # the paper-shaped 1024x256x256 box (67.1 M nodes, one radius-5 swimmer)
+    # in the launch shape the benchmark times it with (XCD-contiguous blocks
+    # of 256 nodes), against the oracle over the whole field: one replayed
+    # 32-step graph and eight steps more
+    case = wl.paper_box()
+    print("paper box", case["shape"], flush=True)
+    o, lat = _run_pair(case, 40, launch=bench.BOX_LAUNCH)
+    du = rel_l2(lat.velocity(), o.velocity())
+    dr = np.abs(lat.markers() - o.markers()).max()
+    print("rel-L2 u", du, "max |dr|", dr, flush=True)
+    assert du < 1e-5
+    assert dr < POS_PER_STEP * 40
+    c = lat.conserved()
+    assert abs(c[0] - 1024 * 256 * 256) < 1e-6 * 1024 * 256 * 256 and np.abs(c[1:]).max() < 1e-6
+
+
 def test_pair_256_parity_few_steps():
     for arr in ("collinear", "side"):
         case = wl.pair_256(seed=0, arrangement=arr)
