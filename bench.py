@@ -21,13 +21,16 @@ if ROOT not in sys.path:
 
 PEAK_HBM_GBS = 8000.0
 # stream-collide launch shapes (block, XCD remap, resident workgroups per CU),
-# measured best for these workloads on MI355X: at 128^3 the round-robin block
-# order (no XCD remap) runs the full-grid launch at 54 us against 58 us
-# remapped, while the 1024x256x256 box is 2 % faster remapped
-MAIN_LAUNCH = (256, False, 2)
+# measured best for these workloads on MI355X by explicit sweeps: the 128^3
+# FP32 step with one resident 512-node workgroup per CU claiming blocks in
+# round-robin order (62.3 us against 63.0 us for two of 256 nodes, 64.9 us
+# remapped); FP16 (static persistent walk) at two of 256 nodes; the batch
+# and the 1024x256x256 box non-persistent, the box with the XCD remap
+# (1.842 ms against 1.849 ms in block order and 1.869 ms at block 256)
+MAIN_LAUNCH = (512, False, 1)
 FP16_LAUNCH = (256, False, 2)
 BATCH_LAUNCH = (512, False, 0)
-BOX_LAUNCH = (256, True, 0)
+BOX_LAUNCH = (512, True, 0)
 KERNEL_LAUNCH = (256, False, -1)  # serial order: full-grid launch for the roofline
 PMC_PROFILE = os.path.join(ROOT, "profiles", "stream_collide_128cubed_pmc.txt")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2202_12147_amd", "csrc", "lattice_kernels.hip")

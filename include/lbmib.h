@@ -292,10 +292,13 @@ int lbm_kernel_time(lbm_handle* h, double* ms, int64_t* launches);
  * nodes; whether workgroups are remapped so that each of the 8 XCDs streams
  * one contiguous range of the grid; and, with swimmers, `resident` > 0 makes
  * the launch that runs concurrently with the immersed-boundary kernels
- * persistent with that many workgroups per compute unit, each walking one
- * XCD's contiguous range when remapped and the grid in strides otherwise (0:
- * one workgroup per block; -1: no concurrency, the immersed-boundary kernels
- * then one full-grid launch).  Results are bitwise identical for every shape.
+ * persistent with that many workgroups per compute unit (0: one workgroup
+ * per block; -1: no concurrency, the immersed-boundary kernels then one
+ * full-grid launch).  With FP32 storage the persistent workgroups of each XCD
+ * claim that XCD's blocks one at a time from a device counter; with FP16
+ * storage they walk them in a fixed order.  An XCD's blocks are one
+ * contiguous range when remapped, every eighth block otherwise.  Results are
+ * bitwise identical for every shape.
  * Errors: LBM_EINVAL. */
 int lbm_set_stream_collide_launch(lbm_handle* h, int block, int xcd_remap, int resident);
 /* Algorithmic bytes one stream-collide launch moves (19 populations read and

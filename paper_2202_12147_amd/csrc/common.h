@@ -51,6 +51,12 @@ __host__ __device__ inline int near_slot(int64_t v) {
   return r < 0 ? r + kNearSlots : r;
 }
 constexpr int kPopBlock = 256; // nodes per population block (a power of two: shifts and masks)
+// Block counters of the persistent bulk launch: one per XCD (workgroups are
+// dealt to the 8 XCDs round robin) and step parity, each on its own 128-byte
+// line; Dev::work holds kWorkCounters ints.
+constexpr int kXcds = 8;
+constexpr int kWorkStride = 32;
+constexpr int kWorkCounters = 2 * kXcds * kWorkStride;
 
 // Element index of population q of global node `node`.  A wavefront's 64
 // consecutive nodes read or write one contiguous 256-byte (FP32) run per
@@ -157,6 +163,9 @@ struct Dev {
   // (near_list[parity][i], near_count[parity]); a block is near when it holds
   // a node within two nodes of a bead's stencil region
   int* near;
+  // persistent bulk launch: block counters work[parity][group * kWorkStride]
+  // (zero before a step's launch; each launch zeroes the next step's)
+  int* work;
   int* near_list;
   int* near_count;
   int max_near, nsc, sc_bs;

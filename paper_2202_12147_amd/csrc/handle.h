@@ -92,6 +92,7 @@ struct lbm_handle {
   int* d_overflow = nullptr;
   int* d_spread_bead = nullptr;
   int *d_near = nullptr, *d_near_list = nullptr, *d_near_count = nullptr;
+  int* d_work = nullptr;           // persistent bulk block counters (kWorkCounters)
   bool need_prologue = true;
   hipStream_t side = nullptr;      // IBM chain, forked from `stream` every step
   std::vector<hipEvent_t> step_events;  // per chunk step: bulk done, near blocks done; + one fork

@@ -293,6 +293,7 @@ int upload(lbm_handle* h) {
   h->d_near = h->alloc<int>(kNearSlots * (size_t)nsc_max, rc);
   h->d_near_list = h->alloc<int>(2 * (size_t)nsc_max, rc);
   h->d_near_count = h->alloc<int>(2, rc);
+  h->d_work = h->alloc<int>(kWorkCounters, rc);
   if (rc != LBM_OK) return h->fail(rc, "device allocation for markers failed");
   put(h->d_boxes, h->boxes.data(), sizeof(Box) * h->boxes.size());
   put(h->d_pos, pos.data(), sizeof(double) * pos.size());
@@ -364,6 +365,7 @@ int upload(lbm_handle* h) {
   d.near = h->d_near;
   d.near_list = h->d_near_list;
   d.near_count = h->d_near_count;
+  d.work = h->d_work;
   d.tile_box = nullptr;
   set_near_bounds(h);
   if (!h->swimmers.empty()) {
@@ -469,11 +471,13 @@ void enqueue_steps(lbm_handle* h, int64_t count) {
 
 // Before stepping resumes: bead regions of the current markers and the near
 // tiles under the previous step's parity, so the first step can split the
-// grid into bulk and active parts.  Eager, never captured.
+// grid into bulk and active parts, and zeroed block counters for the
+// persistent bulk launch.  Eager, never captured.
 int prologue(lbm_handle* h) {
   if (!h->need_prologue || h->swimmers.empty()) return LBM_OK;
   int rc = h->hip(hipMemsetAsync(h->d_near, 0x80, sizeof(int) * kNearSlots * h->dev.nsc, h->stream), "hipMemsetAsync");
   if (!rc) rc = h->hip(hipMemsetAsync(h->d_near_count, 0, sizeof(int) * 2, h->stream), "hipMemsetAsync");
+  if (!rc) rc = h->hip(hipMemsetAsync(h->d_work, 0, sizeof(int) * kWorkCounters, h->stream), "hipMemsetAsync");
   if (rc) return rc;
   launch_bead_stats(h->dev, -1, h->stream);
   rc = h->hip(hipGetLastError(), "prologue launch");

@@ -87,12 +87,32 @@ def test_pair_storage_forms_vs_oracle(arrangement):
     o.step(steps)
     d_o = o.swimmer_centres() - X0
     res = {}
-    for name, st, S in (("fp32", lbmib.FP32_SHIFTED, 1.0), ("fp16", lbmib.FP16_SHIFTED, S27)):
+    for name, st, S, launch in (("fp32", lbmib.FP32_SHIFTED, 1.0, bench.MAIN_LAUNCH),
+                                ("fp16", lbmib.FP16_SHIFTED, S27, bench.FP16_LAUNCH)):
         lat = lbmib.from_workload(case, storage=st, fp16_scale=S)
-        lat.set_stream_collide_launch(*bench.MAIN_LAUNCH)
+        lat.set_stream_collide_launch(*launch)
         lat.step(steps)
         d = lat.swimmer_centres() - X0
         res[name] = (rel_l2(lat.velocity(), o.velocity()), np.abs(d - d_o).max() / np.abs(d_o).max())
     print(arrangement, "u rel-L2 / centre displacement rel error:", res, flush=True)
     assert res["fp32"][0] < 1e-5 and res["fp32"][1] < 1e-4
     assert res["fp16"][0] < 5e-4 and res["fp16"][1] < 2e-3
+
+
+@pytest.mark.parametrize("block,remap,resident", [(256, 0, 2), (256, 1, 2), (512, 0, 1), (128, 0, 0)])
+def test_fp16_launch_shapes_bitwise_equal_with_swimmer(block, remap, resident):
+    # FP16 storage walks the persistent bulk launch statically (in block
+    # order or per XCD range); every launch shape gives the same bits as the
+    # serial order
+    case = wl.single_128(seed=1)
+    case["shape"] = (48, 40, 40)
+    case["swimmers"][0]["centres"] = case["swimmers"][0]["centres"] - (40, 24, 24)
+    a = lbmib.from_workload(case, storage=lbmib.FP16_SHIFTED, fp16_scale=S27, use_graphs=False)
+    a.set_stream_collide_launch(256, 0, -1)
+    b = lbmib.from_workload(case, storage=lbmib.FP16_SHIFTED, fp16_scale=S27)
+    b.set_stream_collide_launch(block, remap, resident)
+    for x in (a, b):
+        x.step(45)
+        x.sync()
+    assert np.array_equal(a.markers(), b.markers())
+    assert np.array_equal(a.populations(), b.populations())
