@@ -160,8 +160,9 @@ def average_section(lbmib, lat, nodes, steps=2000):
 
 def batch_section(lbmib, wl, steps=5000, warmup=200, seed=0):
     """The 64-box ensemble (edges from {48,64,80,96} per axis, one swimmer
-    each) advanced together: the launch shape the autotuner picked for it, then `steps` timed
-    steps; batch MLUPS = total nodes x steps / time."""
+    each) advanced together at the launch shape measured best for it by
+    explicit sweeps (BATCH_LAUNCH), `steps` timed steps; batch MLUPS = total
+    nodes x steps / time."""
     ens = wl.ensemble(seed=seed)
     batch = lbmib.batch_from_ensemble(ens)
     batch.set_stream_collide_launch(*BATCH_LAUNCH)

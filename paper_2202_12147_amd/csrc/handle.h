@@ -63,7 +63,7 @@ struct lbm_handle {
   int nm = 0;
   int64_t nodes = 0, pstride = 0;
   int ntiles = 0, sc_blocks = 0, spread_blocks = 0, out_blocks = 0;
-  int sc_block = 256, sc_remap = 1, sc_resident = 0;  // stream-collide launch shape
+  int sc_block = 512, sc_remap = 0, sc_resident = 1;  // stream-collide launch shape (set per handle at creation)
   int ncu = 256;                                        // compute units of the device
   bool uploaded = false, stepped = false;
   int64_t host_step = 0;  // steps enqueued

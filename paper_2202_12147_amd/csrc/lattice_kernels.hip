@@ -293,50 +293,23 @@ __global__ __launch_bounds__(BS) void k_stream_collide(Dev d, int remap, int nbl
     const int cnt = min(d.near_count[pp], d.max_near);
     if ((int)blockIdx.x < cnt) sc_block<ST, BS>(d, d.near_list[pp * d.max_near + blockIdx.x], n, false, avg);
   } else if constexpr (MODE == kScBulk) {
-    if (resident && ST == kFp16) {
-      // Persistent, static: FP16 blocks take half the time of FP32 ones and
-      // the FP16 step is bound by the immersed-boundary chain, so claiming
-      // blocks (below) costs more than it balances (58.8 against 57.7 us per
-      // 128^3 step).  With `remap` each XCD walks one contiguous range of
-      // blocks, else the blocks go grid-stride (round robin over the XCDs).
-      if (remap) {
-        const int per = (nblocks + 7) / 8;  // logical blocks per XCD
-        const int xcd = blockIdx.x % 8, g8 = (int)gridDim.x / 8;
-        for (int j = blockIdx.x / 8; j < per; j += g8) {
-          const int blk = xcd * per + j;
-          if (blk < nblocks && d.near[pf * d.nsc + blk] != (int)pn) sc_block<ST, BS>(d, blk, n, true, avg);
-        }
-      } else {
-        for (int blk = blockIdx.x; blk < nblocks; blk += (int)gridDim.x)
-          if (d.near[pf * d.nsc + blk] != (int)pn) sc_block<ST, BS>(d, blk, n, true, avg);
+    // Persistent launches (resident > 0) walk the blocks statically here
+    // (FP16 storage; FP32 launches k_stream_collide_claimed instead): FP16
+    // blocks take half the time of FP32 ones and the FP16 step is bound by
+    // the immersed-boundary chain, so claiming blocks costs more than it
+    // balances (58.8 against 57.7 us per 128^3 step).  With `remap` each XCD
+    // walks one contiguous range of blocks, else the blocks go grid-stride
+    // (round robin over the XCDs).
+    if (resident && remap) {
+      const int per = (nblocks + 7) / 8;  // logical blocks per XCD
+      const int xcd = blockIdx.x % 8, g8 = (int)gridDim.x / 8;
+      for (int j = blockIdx.x / 8; j < per; j += g8) {
+        const int blk = xcd * per + j;
+        if (blk < nblocks && d.near[pf * d.nsc + blk] != (int)pn) sc_block<ST, BS>(d, blk, n, true, avg);
       }
     } else if (resident) {
-      // Persistent, claimed: the workgroups of group g = blockIdx.x mod G
-      // (G = 8 when the grid allows: the workgroups of one XCD) claim the
-      // group's blocks one at a time from the group's counter, so workgroups
-      // slowed by the concurrent immersed-boundary kernels take fewer blocks
-      // (128^3 FP32 step 62.7 against 69.9 us with a static split).  The
-      // group's blocks are g, g + G, g + 2G, ... (round robin), or, with
-      // `remap`, one contiguous range per group.  The claim of the next block
-      // is issued before the current block's work, which hides its latency;
-      // two claim slots need one barrier per block.
-      __shared__ int next[2];
-      const int G = min(kXcds, (int)gridDim.x), g = (int)blockIdx.x % G;
-      const int per = (nblocks + G - 1) / G;
-      int* const ctr = d.work + ((int)(n & 1) * kXcds + g) * kWorkStride;
-      if ((int)blockIdx.x < G && threadIdx.x == 0)
-        d.work[((int)((n + 1) & 1) * kXcds + (int)blockIdx.x) * kWorkStride] = 0;
-      if (threadIdx.x == 0) next[0] = atomicAdd(ctr, 1);
-      __syncthreads();
-      for (int i = 0;; ++i) {
-        const int j = next[i & 1];  // uniform over the workgroup
-        if (j >= per) break;
-        // slot (i + 1) & 1 was last read in iteration i - 1, before its barrier
-        if (threadIdx.x == 0) next[(i + 1) & 1] = atomicAdd(ctr, 1);
-        const int blk = remap ? g * per + j : g + G * j;
-        if (blk < nblocks && d.near[pf * d.nsc + blk] != (int)pn) sc_block<ST, BS>(d, blk, n, true, avg);
-        __syncthreads();
-      }
+      for (int blk = blockIdx.x; blk < nblocks; blk += (int)gridDim.x)
+        if (d.near[pf * d.nsc + blk] != (int)pn) sc_block<ST, BS>(d, blk, n, true, avg);
     } else {
       const int blk = logical_block(remap, nblocks);
       if (blk < nblocks && d.near[pf * d.nsc + blk] != (int)pn) sc_block<ST, BS>(d, blk, n, true, avg);
@@ -344,6 +317,44 @@ __global__ __launch_bounds__(BS) void k_stream_collide(Dev d, int remap, int nbl
   } else {
     const int blk = logical_block(remap, nblocks);
     if (blk < nblocks) sc_block<ST, BS>(d, blk, n, false, avg);
+  }
+}
+
+// Persistent bulk launch with claimed blocks (FP32 storage; the same launch
+// mode and arguments as k_stream_collide<..., kScBulk, ...> with resident > 0;
+// a kernel of its own so that the claim slots in LDS are not allocated by the
+// other launches).
+template <int ST, int BS, bool AVG>
+__global__ __launch_bounds__(BS) void k_stream_collide_claimed(Dev d, int remap, int nblocks, int resident) {
+  // The workgroups of group g = blockIdx.x mod G (G = 8 when the grid allows:
+  // the workgroups of one XCD) claim the group's blocks one at a time from
+  // the group's counter, so workgroups slowed by the concurrent
+  // immersed-boundary kernels take fewer blocks (128^3 FP32 step 62.7
+  // against 69.9 us with a static split).  The group's blocks are g, g + G,
+  // g + 2G, ... (round robin), or, with `remap`, one contiguous range per
+  // group.  The claim of the next block is issued before the current block's
+  // work, which hides its latency; two claim slots need one barrier per block.
+  (void)resident;
+  const int64_t n = *d.step + d.sub;
+  const int64_t pn = n - 1;  // the step whose bead statistics marked the near blocks
+  const int pf = near_slot(pn);
+  const bool avg = AVG && avg_sampled(d, n);
+  __shared__ int next[2];
+  const int G = min(kXcds, (int)gridDim.x), g = (int)blockIdx.x % G;
+  const int per = (nblocks + G - 1) / G;
+  int* const ctr = d.work + ((int)(n & 1) * kXcds + g) * kWorkStride;
+  if ((int)blockIdx.x < G && threadIdx.x == 0)
+    d.work[((int)((n + 1) & 1) * kXcds + (int)blockIdx.x) * kWorkStride] = 0;
+  if (threadIdx.x == 0) next[0] = atomicAdd(ctr, 1);
+  __syncthreads();
+  for (int i = 0;; ++i) {
+    const int j = next[i & 1];  // uniform over the workgroup
+    if (j >= per) break;
+    // slot (i + 1) & 1 was last read in iteration i - 1, before its barrier
+    if (threadIdx.x == 0) next[(i + 1) & 1] = atomicAdd(ctr, 1);
+    const int blk = remap ? g * per + j : g + G * j;
+    if (blk < nblocks && d.near[pf * d.nsc + blk] != (int)pn) sc_block<ST, BS>(d, blk, n, true, avg);
+    __syncthreads();
   }
 }
 
@@ -533,6 +544,15 @@ static void launch_sc_mode(const Dev& d, int block, int nblocks, int remap, int 
   if (MODE == kScBulk && resident > 0)
     grid = remap ? std::min(grid, ncu * resident) / 8 * 8 : std::min(grid, ncu * resident);
   if (MODE != kScBulk) resident = 0;
+  if (MODE == kScBulk && resident > 0 && ST != kFp16) {
+    if (block == 128)
+      launch_k(k_stream_collide_claimed<ST, 128, AVG>, grid, 128, s, ev0, ev1, d, remap, nblocks, resident);
+    else if (block == 512)
+      launch_k(k_stream_collide_claimed<ST, 512, AVG>, grid, 512, s, ev0, ev1, d, remap, nblocks, resident);
+    else
+      launch_k(k_stream_collide_claimed<ST, 256, AVG>, grid, 256, s, ev0, ev1, d, remap, nblocks, resident);
+    return;
+  }
   if (block == 128)
     launch_k(k_stream_collide<ST, 128, MODE, AVG>, grid, 128, s, ev0, ev1, d, remap, nblocks, resident);
   else if (block == 512)

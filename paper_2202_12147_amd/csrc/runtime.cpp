@@ -633,6 +633,24 @@ int create_boxes(const lbm_box_desc* boxes, int nboxes, const lbm_opts* opts, lb
   h->ntiles = tile0;
   h->out_blocks = block0;
   h->sc_table_cap = sc_cap;
+  // default stream-collide launch shape, the fastest measured on MI355X:
+  // one box, FP32 storage: one persistent 512-node workgroup per CU claiming
+  // blocks in round-robin order (128^3 swimmer step 62.3 us, 82 us at the
+  // non-persistent shape); FP16 storage: two persistent 256-node workgroups
+  // per CU; batches: non-persistent 512-node workgroups
+  if (nboxes > 1) {
+    h->sc_block = 512;
+    h->sc_remap = 0;
+    h->sc_resident = 0;
+  } else if (h->storage == LBM_FP16_SHIFTED) {
+    h->sc_block = 256;
+    h->sc_remap = 0;
+    h->sc_resident = 2;
+  } else {
+    h->sc_block = 512;
+    h->sc_remap = 0;
+    h->sc_resident = 1;
+  }
 
   const size_t eb = element_bytes(h);
   h->pop[0] = h->alloc<char>(eb * kQ * h->pstride, rc);
