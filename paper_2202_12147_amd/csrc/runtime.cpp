@@ -1379,7 +1379,10 @@ int lbm_autotune(lbm_handle* h, int32_t steps, const char* cache_path, char* rep
     int block, remap, resident;
   };
   std::vector<Cand> cands;
-  const std::vector<int> residents = h->swimmers.empty() ? std::vector<int>{0} : std::vector<int>{-1, 0, 2, 6};
+  // resident workgroups per CU of the concurrent bulk launch: serial order,
+  // one per block, and the persistent counts that measured fastest (more than
+  // two leave too few slots to the concurrent immersed-boundary kernels)
+  const std::vector<int> residents = h->swimmers.empty() ? std::vector<int>{0} : std::vector<int>{-1, 0, 1, 2};
   for (int blk : {128, 256, 512})
     for (int remap : {0, 1})
       for (int res : residents) cands.push_back({blk, remap, res});
