@@ -74,6 +74,28 @@ def test_batch_average_per_box():
         print("box", i, "rel-L2 mean u", rel_l2(mg, mo), flush=True)
         assert ng == no == 26
         assert rel_l2(mg, mo) < 1e-5
+        # device output of one box of a batch (staged, then copied)
+        t, nt = b.average_velocity(i, device="cuda:0")
+        assert nt == ng and np.array_equal(t.cpu().numpy(), mg)
+
+
+def test_launch_shape_change_keeps_the_average():
+    # a new launch shape mid-average drops and recaptures the step graphs;
+    # the sums, the schedule and every bit of the mean carry on
+    case = wl.small_case()
+    a = lbmib.from_workload(case)
+    b = lbmib.from_workload(case)
+    for x in (a, b):
+        x.step(5)
+        x.average_begin(3)
+        x.step(40)
+    b.set_stream_collide_launch(256, 1, 2)
+    for x in (a, b):
+        x.step(37)
+    ma, na = a.average_velocity()
+    mb, nb = b.average_velocity()
+    assert na == nb == 26
+    assert np.array_equal(ma, mb)
 
 
 def test_fp16_storage_average():
