@@ -108,7 +108,8 @@ typedef struct lbm_handle lbm_handle;
 /* ---- lifetime --------------------------------------------------------------- */
 /* Create a periodic D3Q19 BGK fluid at rest (rho = 1, u = 0), relaxation time
  * tau (Eq. lbe; viscosity nu = (tau - 1/2)/3, Sec. 2.1).  Requires tau > 1/2,
- * every grid edge >= 16, forcing and opts valid.  opts may be NULL (FP32,
+ * every grid edge >= 16, at most 2^31 - 2^16 nodes (a batch: per box, and
+ * fewer than 2^31 in all), forcing and opts valid.  opts may be NULL (FP32,
  * 3-point kernel, graphs on, own stream).  *out receives the handle.
  * Errors: LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE. */
 int lbm_create(const lbm_grid* grid, double tau, int forcing, const lbm_opts* opts,

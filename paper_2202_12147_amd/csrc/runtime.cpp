@@ -562,7 +562,9 @@ int create_boxes(const lbm_box_desc* boxes, int nboxes, const lbm_opts* opts, lb
     const lbm_box_desc& d = boxes[b];
     if (!(d.tau > 0.5) || !std::isfinite(d.tau)) return LBM_EINVAL;
     if (d.grid.nx < 16 || d.grid.ny < 16 || d.grid.nz < 16) return LBM_EINVAL;
-    if ((int64_t)d.grid.nx * d.grid.ny * d.grid.nz >= (int64_t)1 << 31) return LBM_EINVAL;
+    // node offsets within a box are 32-bit in the kernels (a lane index plus a
+    // neighbour offset of up to n nodes), so a box stays 2^16 below 2^31
+    if ((int64_t)d.grid.nx * d.grid.ny * d.grid.nz > ((int64_t)1 << 31) - ((int64_t)1 << 16)) return LBM_EINVAL;
     if (d.forcing != LBM_GUO && d.forcing != LBM_SHAN_CHEN) return LBM_EINVAL;
     total += (int64_t)d.grid.nx * d.grid.ny * d.grid.nz;
   }
