@@ -221,3 +221,36 @@ def test_largest_box_matches_a_small_box_near_the_swimmer():
         assert abs(c[0] - n) < 1e-9 * n and np.abs(c[1:]).max() < 1e-6
     finally:
         b.close()
+
+
+def test_zero_steps_change_nothing():
+    case = wl.small_case()
+    lat = lbmib.from_workload(case)
+    lat.step(7)
+    m, p = lat.markers(), lat.populations()
+    lat.step(0)
+    assert lat.time == 7
+    assert np.array_equal(lat.markers(), m) and np.array_equal(lat.populations(), p)
+    ens = wl.ensemble(seed=2, nboxes=2)
+    b = lbmib.batch_from_ensemble(ens)
+    b.step(0)
+    assert b.time == 0 and not b.populations().any()
+
+
+def test_without_actuation_the_swimmer_stays_put():
+    """A = B = 0 (Sec. 2.2): the stress-free beads feel no spring, Skalak or
+    bending force and the volume term sees only the rounding of V - V0, so
+    over 200 steps the markers stay where they were and the fluid at rest,
+    up to that rounding (the oracle does the same)."""
+    case = wl.small_case()
+    case["swimmers"] = [wl.swimmer((16, 16, 16), 10.0, A=0.0, T=500.0)]
+    o = oracle_from(case)
+    lat = lbmib.from_workload(case)
+    r0 = lat.markers()
+    o.step(200)
+    lat.step(200)
+    dr = np.abs(lat.markers() - r0).max()
+    umax = np.abs(lat.velocity()).max()
+    print("max |dr|", dr, "max |u|", umax, "oracle max |dr|", np.abs(o.markers() - r0).max(), flush=True)
+    assert dr < 1e-12 and umax < 1e-12
+    assert np.abs(o.markers() - r0).max() < 1e-12
