@@ -117,3 +117,25 @@ def test_autotune_restores_state_and_caches(tmp_path):
     assert np.array_equal(a.populations(), b.populations())
     assert a.time == b.time == 65
     assert a.autotune(16, cache).startswith("cached")
+
+
+def test_batch_with_an_empty_box_equals_single_boxes():
+    # the middle box holds no swimmer (a gap in the bead -> box tables) and
+    # runs Shan-Chen forcing; every box equals its own single-box run bit for bit
+    s1 = wl.small_case()
+    empty = dict(shape=(24, 20, 17), tau=0.7, forcing=wl.SHAN_CHEN, width=3, swimmers=[])
+    s3 = dict(wl.small_case(), shape=(40, 32, 36), tau=0.9,
+              swimmers=[wl.swimmer((20, 16, 18), 9.0, A=8e-4, T=400.0, alpha=1.0)])
+    ens = dict(boxes=[s1, empty, s3])
+    batch = lbmib.batch_from_ensemble(ens)
+    singles = [lbmib.from_workload(c) for c in ens["boxes"]]
+    batch.step(60)
+    for x in singles:
+        x.step(60)
+    for i, x in enumerate(singles):
+        assert np.array_equal(batch.velocity(i), x.velocity())
+    assert not batch.velocity(1).any()
+    nv = singles[0].n_markers
+    markers = batch.markers()
+    assert np.array_equal(markers[:nv], singles[0].markers())
+    assert np.array_equal(markers[nv:], singles[2].markers())
