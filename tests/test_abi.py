@@ -41,7 +41,20 @@ def test_invalid_arguments_rejected():
     bad = lbmib.Opts(1, 3, 3.0, 1, None)
     assert lib.lbm_create(C.byref(ok), 1.0, 0, C.byref(bad), C.byref(h)) == -1  # scale not 2^k
     assert lib.lbm_create(None, 1.0, 0, None, C.byref(h)) == -1
+    bad = lbmib.Opts(9, 3, 1.0, 1, None)
+    assert lib.lbm_create(C.byref(ok), 1.0, 0, C.byref(bad), C.byref(h)) == -1  # bad storage
+    # one box holds at most 2^31 - 2^16 nodes (32-bit node offsets in the kernels)
+    assert lib.lbm_create(C.byref(lbmib.Grid(2048, 1024, 1024)), 1.0, 0, None, C.byref(h)) == -1
+    assert lib.lbm_create(C.byref(lbmib.Grid(65535, 128, 256)), 1.0, 0, None, C.byref(h)) == -1
+    # a batch holds fewer than 2^31 nodes in all, and at least one box
+    boxes = (lbmib.BoxDesc * 2)(lbmib.BoxDesc(lbmib.Grid(1024, 1024, 1024), 1.0, 0),
+                                lbmib.BoxDesc(lbmib.Grid(1024, 1024, 1024), 1.0, 0))
+    assert lib.lbm_batch_create(boxes, 2, None, C.byref(h)) == -1
+    assert lib.lbm_batch_create(boxes, 0, None, C.byref(h)) == -1
     assert h.value is None
+    count = C.c_int64()
+    assert lib.lbm_average_begin(None, 1) == -1
+    assert lib.lbm_get_average_velocity(None, 0, None, 0, C.byref(count)) == -1
     desc = lbmib.AdjointDesc(10, 5, 0, 0)
     J, g = C.c_double(), (C.c_double * 4)()
     assert lib.lbm_adjoint(None, C.byref(desc), C.byref(J), g) == -1
