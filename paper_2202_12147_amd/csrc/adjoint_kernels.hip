@@ -162,7 +162,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(Dev d, Adj a, int nblock
   const float cq[kQ] = {0.0f,       btx,        -btx,       bty,        -bty,       btz,        -btz,
                         btx + bty,  -btx - bty, btx - bty,  bty - btx,  btx + btz,  -btx - btz, btx - btz,
                         btz - btx,  bty + btz,  -bty - btz, bty - btz,  btz - bty};
-  if (d.wt_stores) {
+  if (d.small_pops) {
 #pragma unroll
     for (int q = 0; q < kQ; ++q) stream_store(a.Ldst + pop_index(q, base), k1 * L[q] + a0 + cq[q]);
   } else {

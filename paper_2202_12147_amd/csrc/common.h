@@ -38,7 +38,7 @@ constexpr int kNearSlots = 3;
 // cache (128^3 FP32: 45.5 us per sweep against 54.3 us with non-temporal
 // stores; 45.9 us with plain stores, which slow the concurrent kernels) and
 // costs 6 % on a 7.7 GB batch, so handles use it up to kWriteThroughBytes of
-// population storage (Dev::wt_stores) and non-temporal stores above.
+// population storage (Dev::small_pops) and non-temporal stores above.
 __device__ inline void stream_store(float* p, float v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
@@ -169,7 +169,11 @@ struct Dev {
   int* near_list;
   int* near_count;
   int max_near, nsc, sc_bs;
-  int wt_stores;          // population stores written through (stream_store) or non-temporal
+  // 1 when both population sets take at most kWriteThroughBytes: the
+  // streaming stores are written through (stream_store) and the pulls are
+  // non-temporal loads, which lets the last-level cache serve part of the
+  // traffic; 0 above: non-temporal stores and plain (cached) pulls
+  int small_pops;
   const int* tile_box;   // tile -> box (batches only)
   int* overflow;         // set when a bead region outgrows its reserved tiles
   int spread_blocks;

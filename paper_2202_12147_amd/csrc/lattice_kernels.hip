@@ -44,6 +44,7 @@ template <>
 struct PopIO<kFp32> {
   using T = float;
   __device__ static inline float ld(const float* p, int, float) { return __builtin_nontemporal_load(p); }
+  __device__ static inline float ld_cached(const float* p, int, float) { return *p; }
   __device__ static inline void st(float* p, int, float v, float) { __builtin_nontemporal_store(v, p); }
   __device__ static inline void st_wt(float* p, int, float v, float) { stream_store(p, v); }
 };
@@ -52,6 +53,7 @@ template <>
 struct PopIO<kFp16> {
   using T = __half;
   __device__ static inline float ld(const __half* p, int, float inv) { return __half2float(*p) * inv; }
+  __device__ static inline float ld_cached(const __half* p, int q, float inv) { return ld(p, q, inv); }
   __device__ static inline void st(__half* p, int, float v, float scale) { *p = __float2half_rn(v * scale); }
   __device__ static inline void st_wt(__half* p, int, float v, float scale) {
     stream_store(reinterpret_cast<unsigned short*>(p), __half_as_ushort(__float2half_rn(v * scale)));
@@ -66,6 +68,7 @@ struct PopIO<kFp32Plain> {
   __device__ static inline float ld(const float* p, int q, float) {
     return __builtin_nontemporal_load(p) - weight(q);
   }
+  __device__ static inline float ld_cached(const float* p, int q, float) { return *p - weight(q); }
   __device__ static inline void st(float* p, int q, float v, float) { __builtin_nontemporal_store(v + weight(q), p); }
   __device__ static inline void st_wt(float* p, int q, float v, float) { stream_store(p, v + weight(q)); }
 };
@@ -88,7 +91,10 @@ __device__ inline Nbr neighbours(int x, int y, int z, int nx, int ny, int nz) {
 }
 
 // Pull the 19 deviations of node `base` from the source populations.
-template <int ST>
+// NTLD: non-temporal loads (populations of the last-level-cache size) or
+// plain ones (larger sets: 2 % faster on 10 GB of populations, 8 % slower at
+// 128^3).
+template <int ST, bool NTLD = true>
 __device__ inline void pull(const typename PopIO<ST>::T* __restrict__ src, int64_t base, const Nbr& o, float inv,
                             float* g) {
   using IO = PopIO<ST>;
@@ -105,7 +111,11 @@ __device__ inline void pull(const typename PopIO<ST>::T* __restrict__ src, int64
   for (int q = 0; q < kQ; ++q) {
     const int rel = lane + off[q];
     const int db = rel >> 8;  // floor(rel / kPopBlock): arithmetic shift, kPopBlock = 256
-    g[q] = IO::ld(bp + (int64_t)db * (kQ * kPopBlock) + (q * kPopBlock + (rel & (kPopBlock - 1))), q, inv);
+    const typename PopIO<ST>::T* a = bp + (int64_t)db * (kQ * kPopBlock) + (q * kPopBlock + (rel & (kPopBlock - 1)));
+    if constexpr (NTLD)
+      g[q] = IO::ld(a, q, inv);
+    else
+      g[q] = IO::ld_cached(a, q, inv);
   }
 }
 
@@ -162,7 +172,7 @@ __device__ inline int logical_block(int remap, int nblocks) {
 // `forced`: read F and write u at this node (its tile is active this step).
 // `avg`: add u to the node's time-average sums (a sampled step).
 // MOM: also record (rho, u) of the node in d.mom.
-template <int ST, bool MOM = false>
+template <int ST, bool MOM = false, bool NTLD = true>
 __device__ inline void sc_node(const Dev& d, const Box& B, int x, int y, int z, int64_t base,
                                int64_t n, bool forced, bool avg) {
   using IO = PopIO<ST>;
@@ -180,7 +190,7 @@ __device__ inline void sc_node(const Dev& d, const Box& B, int x, int y, int z, 
     a2 = d.uavg[2 * ps + base];
   }
   float g[kQ];
-  pull<ST>(src, base, o, d.fp16_inv, g);
+  pull<ST, NTLD>(src, base, o, d.fp16_inv, g);
   const Moments m = moments(g);
 
   float Fx = B.gx, Fy = B.gy, Fz = B.gz;
@@ -229,7 +239,7 @@ __device__ inline void sc_node(const Dev& d, const Box& B, int x, int y, int z, 
   collide_pair(g[15], g[16], kW2, om, m.drho, m.rho, usq15, ey + ez, src_a, uy + uz, Fy + Fz, uf);
   collide_pair(g[17], g[18], kW2, om, m.drho, m.rho, usq15, ey - ez, src_a, uy - uz, Fy - Fz, uf);
   T* const bq = dst + (base / kPopBlock) * (int64_t)(kQ * kPopBlock) + (int)(base % kPopBlock);
-  if (d.wt_stores) {
+  if (d.small_pops) {
 #pragma unroll
     for (int q = 0; q < kQ; ++q) IO::st_wt(bq + q * kPopBlock, q, g[q], d.fp16_scale);
   } else {
@@ -260,7 +270,7 @@ __device__ inline bool avg_sampled(const Dev& d, int64_t n) {
 //             tile is active.
 constexpr int kScAll = kLaunchAll, kScBulk = kLaunchBulk, kScActive = kLaunchActive;
 
-template <int ST, int BS, bool MOM = false>
+template <int ST, int BS, bool MOM = false, bool NTLD = true>
 __device__ inline void sc_block(const Dev& d, int blk, int64_t n, bool bulk, bool avg) {
   const int b = d.nboxes == 1 ? 0 : d.sc_block_box[blk];
   const Box B = d.boxes[b];
@@ -278,12 +288,12 @@ __device__ inline void sc_block(const Dev& d, int blk, int64_t n, bool bulk, boo
     const int tile = B.tile0 + (x / kTile) + B.tx * ((y / kTile) + B.ty * (z / kTile));
     forced = d.stamp[tile] == (int)n;
   }
-  sc_node<ST, MOM>(d, B, x, y, z, B.node0 + id, n, forced, avg);
+  sc_node<ST, MOM, NTLD>(d, B, x, y, z, B.node0 + id, n, forced, avg);
 }
 
 // AVG: the variant launched while a time average of u runs (the sampling
 // test and the sums); without it the averaging code is compiled out.
-template <int ST, int BS, int MODE, bool AVG>
+template <int ST, int BS, int MODE, bool AVG, bool NTLD>
 __global__ __launch_bounds__(BS) void k_stream_collide(Dev d, int remap, int nblocks, int resident) {
   const int64_t n = *d.step + d.sub;
   const int64_t pn = n - 1;  // the step whose bead statistics marked the near blocks
@@ -291,7 +301,8 @@ __global__ __launch_bounds__(BS) void k_stream_collide(Dev d, int remap, int nbl
   const bool avg = AVG && avg_sampled(d, n);
   if constexpr (MODE == kScActive) {
     const int cnt = min(d.near_count[pp], d.max_near);
-    if ((int)blockIdx.x < cnt) sc_block<ST, BS>(d, d.near_list[pp * d.max_near + blockIdx.x], n, false, avg);
+    if ((int)blockIdx.x < cnt)
+      sc_block<ST, BS, false, NTLD>(d, d.near_list[pp * d.max_near + blockIdx.x], n, false, avg);
   } else if constexpr (MODE == kScBulk) {
     // Persistent launches (resident > 0) walk the blocks statically here
     // (FP16 storage; FP32 launches k_stream_collide_claimed instead): FP16
@@ -305,18 +316,18 @@ __global__ __launch_bounds__(BS) void k_stream_collide(Dev d, int remap, int nbl
       const int xcd = blockIdx.x % 8, g8 = (int)gridDim.x / 8;
       for (int j = blockIdx.x / 8; j < per; j += g8) {
         const int blk = xcd * per + j;
-        if (blk < nblocks && d.near[pf * d.nsc + blk] != (int)pn) sc_block<ST, BS>(d, blk, n, true, avg);
+        if (blk < nblocks && d.near[pf * d.nsc + blk] != (int)pn) sc_block<ST, BS, false, NTLD>(d, blk, n, true, avg);
       }
     } else if (resident) {
       for (int blk = blockIdx.x; blk < nblocks; blk += (int)gridDim.x)
-        if (d.near[pf * d.nsc + blk] != (int)pn) sc_block<ST, BS>(d, blk, n, true, avg);
+        if (d.near[pf * d.nsc + blk] != (int)pn) sc_block<ST, BS, false, NTLD>(d, blk, n, true, avg);
     } else {
       const int blk = logical_block(remap, nblocks);
-      if (blk < nblocks && d.near[pf * d.nsc + blk] != (int)pn) sc_block<ST, BS>(d, blk, n, true, avg);
+      if (blk < nblocks && d.near[pf * d.nsc + blk] != (int)pn) sc_block<ST, BS, false, NTLD>(d, blk, n, true, avg);
     }
   } else {
     const int blk = logical_block(remap, nblocks);
-    if (blk < nblocks) sc_block<ST, BS>(d, blk, n, false, avg);
+    if (blk < nblocks) sc_block<ST, BS, false, NTLD>(d, blk, n, false, avg);
   }
 }
 
@@ -324,7 +335,7 @@ __global__ __launch_bounds__(BS) void k_stream_collide(Dev d, int remap, int nbl
 // mode and arguments as k_stream_collide<..., kScBulk, ...> with resident > 0;
 // a kernel of its own so that the claim slots in LDS are not allocated by the
 // other launches).
-template <int ST, int BS, bool AVG>
+template <int ST, int BS, bool AVG, bool NTLD>
 __global__ __launch_bounds__(BS) void k_stream_collide_claimed(Dev d, int remap, int nblocks, int resident) {
   // The workgroups of group g = blockIdx.x mod G (G = 8 when the grid allows:
   // the workgroups of one XCD) claim the group's blocks one at a time from
@@ -353,7 +364,7 @@ __global__ __launch_bounds__(BS) void k_stream_collide_claimed(Dev d, int remap,
     // slot (i + 1) & 1 was last read in iteration i - 1, before its barrier
     if (threadIdx.x == 0) next[(i + 1) & 1] = atomicAdd(ctr, 1);
     const int blk = remap ? g * per + j : g + G * j;
-    if (blk < nblocks && d.near[pf * d.nsc + blk] != (int)pn) sc_block<ST, BS>(d, blk, n, true, avg);
+    if (blk < nblocks && d.near[pf * d.nsc + blk] != (int)pn) sc_block<ST, BS, false, NTLD>(d, blk, n, true, avg);
     __syncthreads();
   }
 }
@@ -536,7 +547,7 @@ static void launch_k(K kernel, int grid, int block, hipStream_t s, hipEvent_t ev
     hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), 0, s, d, remap, nblocks, resident);
 }
 
-template <int ST, int MODE, bool AVG>
+template <int ST, int MODE, bool AVG, bool NTLD>
 static void launch_sc_mode(const Dev& d, int block, int nblocks, int remap, int resident, int ncu,
                            hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   int grid = remap ? (nblocks + 7) / 8 * 8 : nblocks;
@@ -546,30 +557,40 @@ static void launch_sc_mode(const Dev& d, int block, int nblocks, int remap, int 
   if (MODE != kScBulk) resident = 0;
   if (MODE == kScBulk && resident > 0 && ST != kFp16) {
     if (block == 128)
-      launch_k(k_stream_collide_claimed<ST, 128, AVG>, grid, 128, s, ev0, ev1, d, remap, nblocks, resident);
+      launch_k(k_stream_collide_claimed<ST, 128, AVG, NTLD>, grid, 128, s, ev0, ev1, d, remap, nblocks, resident);
     else if (block == 512)
-      launch_k(k_stream_collide_claimed<ST, 512, AVG>, grid, 512, s, ev0, ev1, d, remap, nblocks, resident);
+      launch_k(k_stream_collide_claimed<ST, 512, AVG, NTLD>, grid, 512, s, ev0, ev1, d, remap, nblocks, resident);
     else
-      launch_k(k_stream_collide_claimed<ST, 256, AVG>, grid, 256, s, ev0, ev1, d, remap, nblocks, resident);
+      launch_k(k_stream_collide_claimed<ST, 256, AVG, NTLD>, grid, 256, s, ev0, ev1, d, remap, nblocks, resident);
     return;
   }
   if (block == 128)
-    launch_k(k_stream_collide<ST, 128, MODE, AVG>, grid, 128, s, ev0, ev1, d, remap, nblocks, resident);
+    launch_k(k_stream_collide<ST, 128, MODE, AVG, NTLD>, grid, 128, s, ev0, ev1, d, remap, nblocks, resident);
   else if (block == 512)
-    launch_k(k_stream_collide<ST, 512, MODE, AVG>, grid, 512, s, ev0, ev1, d, remap, nblocks, resident);
+    launch_k(k_stream_collide<ST, 512, MODE, AVG, NTLD>, grid, 512, s, ev0, ev1, d, remap, nblocks, resident);
   else
-    launch_k(k_stream_collide<ST, 256, MODE, AVG>, grid, 256, s, ev0, ev1, d, remap, nblocks, resident);
+    launch_k(k_stream_collide<ST, 256, MODE, AVG, NTLD>, grid, 256, s, ev0, ev1, d, remap, nblocks, resident);
 }
 
+template <int ST, bool AVG, bool NTLD>
+static void launch_sc_ld(const Dev& d, int mode, int block, int nblocks, int remap, int resident,
+                         int ncu, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+  if (mode == kScBulk)
+    launch_sc_mode<ST, kScBulk, AVG, NTLD>(d, block, nblocks, remap, resident, ncu, s, ev0, ev1);
+  else if (mode == kScActive)
+    launch_sc_mode<ST, kScActive, AVG, NTLD>(d, block, nblocks, remap, resident, ncu, s, ev0, ev1);
+  else
+    launch_sc_mode<ST, kScAll, AVG, NTLD>(d, block, nblocks, remap, resident, ncu, s, ev0, ev1);
+}
+
+// FP16 pulls are plain loads in either regime (one instance)
 template <int ST, bool AVG>
 static void launch_sc_avg(const Dev& d, int mode, int block, int nblocks, int remap, int resident,
                           int ncu, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
-  if (mode == kScBulk)
-    launch_sc_mode<ST, kScBulk, AVG>(d, block, nblocks, remap, resident, ncu, s, ev0, ev1);
-  else if (mode == kScActive)
-    launch_sc_mode<ST, kScActive, AVG>(d, block, nblocks, remap, resident, ncu, s, ev0, ev1);
+  if (d.small_pops || ST == kFp16)
+    launch_sc_ld<ST, AVG, true>(d, mode, block, nblocks, remap, resident, ncu, s, ev0, ev1);
   else
-    launch_sc_mode<ST, kScAll, AVG>(d, block, nblocks, remap, resident, ncu, s, ev0, ev1);
+    launch_sc_ld<ST, AVG, false>(d, mode, block, nblocks, remap, resident, ncu, s, ev0, ev1);
 }
 
 template <int ST>

@@ -713,7 +713,7 @@ int create_boxes(const lbm_box_desc* boxes, int nboxes, const lbm_opts* opts, lb
   d.step = h->d_step;
   d.sub = 0;
   d.fp16_scale = h->fp16_scale;
-  d.wt_stores = 2 * kQ * h->pstride * (int64_t)element_bytes(h) <= kWriteThroughBytes ? 1 : 0;
+  d.small_pops = 2 * kQ * h->pstride * (int64_t)element_bytes(h) <= kWriteThroughBytes ? 1 : 0;
   d.fp16_inv = 1.0f / h->fp16_scale;
   d.width = h->width;
   d.overflow = h->d_overflow;
