@@ -25,11 +25,12 @@ PEAK_HBM_GBS = 8000.0
 # FP32 step with one resident 512-node workgroup per CU claiming blocks in
 # round-robin order (62.3 us against 63.0 us for two of 256 nodes, 64.9 us
 # remapped); FP16 (static persistent walk) at two of 256 nodes; the batch
-# and the 1024x256x256 box non-persistent, the box with the XCD remap
-# (1.842 ms against 1.849 ms in block order and 1.869 ms at block 256)
+# and the 1024x256x256 box non-persistent with the XCD remap (batch 724.7
+# against 729.5 us in block order, 760-940 us persistent; box 1.842 ms
+# against 1.849 ms in block order and 1.869 ms at block 256)
 MAIN_LAUNCH = (512, False, 1)
 FP16_LAUNCH = (256, False, 2)
-BATCH_LAUNCH = (512, False, 0)
+BATCH_LAUNCH = (512, True, 0)
 BOX_LAUNCH = (512, True, 0)
 KERNEL_LAUNCH = (256, False, -1)  # serial order: full-grid launch for the roofline
 PMC_PROFILE = os.path.join(ROOT, "profiles", "stream_collide_128cubed_pmc.txt")

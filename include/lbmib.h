@@ -301,7 +301,7 @@ int lbm_kernel_time(lbm_handle* h, double* ms, int64_t* launches);
  * contiguous range when remapped, every eighth block otherwise.  Results are
  * bitwise identical for every shape.  Defaults (the fastest measured on
  * MI355X): one box with FP32 storage 512 / no remap / 1; FP16 storage
- * 256 / no remap / 2; batches 512 / no remap / 0.
+ * 256 / no remap / 2; batches 512 / remap / 0.
  * Errors: LBM_EINVAL. */
 int lbm_set_stream_collide_launch(lbm_handle* h, int block, int xcd_remap, int resident);
 /* Algorithmic bytes one stream-collide launch moves (19 populations read and
