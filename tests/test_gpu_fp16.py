@@ -116,3 +116,21 @@ def test_fp16_launch_shapes_bitwise_equal_with_swimmer(block, remap, resident):
         x.sync()
     assert np.array_equal(a.markers(), b.markers())
     assert np.array_equal(a.populations(), b.populations())
+
+
+def test_fp16_above_the_write_through_size():
+    # 256^3 with FP16 storage holds 1.27 GB of populations, above the 1 GiB
+    # up to which stores are written through: the large-set store path of
+    # FP16 against the oracle over ten steps (one-step bars: velocity 2e-3;
+    # markers move ~2.5e-5 per step with a 5e-4 relative FP16 error)
+    case = wl.small_case()
+    case["shape"] = (256, 256, 256)
+    case["swimmers"] = [wl.swimmer((128, 128, 128), 10.0, A=1e-3, T=500.0, phi0=1.0)]
+    o = oracle_from(case)
+    lat = lbmib.from_workload(case, storage=lbmib.FP16_SHIFTED, fp16_scale=S27)
+    o.step(10)
+    lat.step(10)
+    du = rel_l2(lat.velocity(), o.velocity())
+    dr = np.abs(lat.markers() - o.markers()).max()
+    print("fp16 256^3: u rel-L2", du, "max |dr|", dr, flush=True)
+    assert du < 2e-3 and dr < 1e-6
