@@ -159,6 +159,25 @@ def average_section(lbmib, lat, nodes, steps=2000):
     return res
 
 
+def seeds_section(lbmib, wl, seeds=(1, 2), steps=4000, warmup=200):
+    """The 128^3 workload drawn with other seeds (phase offset, radius and
+    rest-length jitter) at the same launch shape: MLUPS per seed."""
+    out = {}
+    for seed in seeds:
+        case = wl.single_128(seed=seed)
+        nodes = case["shape"][0] * case["shape"][1] * case["shape"][2]
+        lat = lbmib.from_workload(case)
+        lat.set_stream_collide_launch(*MAIN_LAUNCH)
+        lat.step(warmup)
+        lat.sync()
+        t0 = time.perf_counter()
+        lat.step(steps)
+        lat.sync()
+        out[str(seed)] = round(nodes * steps / (time.perf_counter() - t0) / 1e6, 1)
+        lat.close()
+    return {"unit": "MLUPS", "steps": steps, "value_by_seed": out}
+
+
 def batch_section(lbmib, wl, steps=5000, warmup=200, seed=0):
     """The 64-box ensemble (edges from {48,64,80,96} per axis, one swimmer
     each) advanced together at the launch shape measured best for it by
@@ -316,6 +335,7 @@ def main():
         import numpy as np
         gmax = float(np.abs(lat.populations()).max())
         out["average"] = average_section(lbmib, lat, nodes)
+        out["seeds"] = seeds_section(lbmib, wl)
         out["fp16"] = fp16_section(lbmib, wl, case, args.steps, args.warmup, gmax)
         del lat
         out["batch"] = batch_section(lbmib, wl)
