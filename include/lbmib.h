@@ -229,6 +229,24 @@ int lbm_batch_get_velocity(lbm_handle* h, int32_t box, float* dst, int on_device
 /* Conserved sums (as lbm_get_conserved) of one box; box = -1 sums all boxes. */
 int lbm_batch_get_conserved(lbm_handle* h, int32_t box, double out[4]);
 
+/* For callers that cannot allocate device memory or wait on the host (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the conserved sums of lbm_batch_get_conserved (box = -1: all
+ * boxes), enqueued on the handle's stream without allocating and without
+ * synchronising.  dst: caller device memory of 4 float64, receives
+ * dst[0] = sum f* (the weights included, one per node) and dst[1..3] =
+ * sum f* c once the stream reaches the work; no finiteness check (read dst
+ * after synchronising the stream).  parts: workgroups of the first reduction
+ * stage, 1..4096 (lbm_batch_get_conserved uses 1024, and gives the same bits
+ * at that value).  Their partial sums go to one static device array of the
+ * library, 4096 x 4 float64 = 128 KiB per GPU, held until the process ends
+ * and shared by every call on that GPU: calls that overlap on one GPU (two
+ * streams or two host threads) race on it.  Every call overwrites the
+ * `parts` entries it reads, so nothing has to start at zero.
+ * Errors: LBM_EINVAL (null handle or dst, box out of range, parts outside
+ * 1..4096), LBM_ESTATE, LBM_EDEVICE. */
+int lbm_batch_get_conserved_noalloc(lbm_handle* h, int32_t box, int32_t parts, double* dst);
+
 /* Autotuner for the stream-collide launch shape (see
  * lbm_set_stream_collide_launch): times every candidate shape over
  * `steps_per_candidate` steps from a device snapshot of the state, restores

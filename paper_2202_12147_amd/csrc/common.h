@@ -208,8 +208,17 @@ void launch_velocity(const Dev& d, int storage, int nblocks, float* u_out, float
 // Mean velocity from the sums d.uavg over `count` samples (zero when count is
 // 0), written box after box as [box][3][n_box] like launch_velocity.
 void launch_average_out(const Dev& d, int nblocks, int64_t count, float* u_out, hipStream_t s);
+// Two-stage FP64 sums of f* and f* c: `nparts` workgroups write partial sums
+// to partial[4 * nparts], one workgroup folds them into out[4] and adds mass0
+// to out[0].
 void launch_conserved(const Dev& d, int storage, int box, double* partial, int nparts, double* out,
-                      hipStream_t s);
+                      hipStream_t s, double mass0);
+// Partial sums held by the allocation-free conserved-sum call: a static device
+// array of kNoAllocParts x 4 doubles per GPU.  resolve_conserved_scratch gives
+// its address on `device`, which must be the current device on the first call
+// for that device (the address is looked up once and kept).
+constexpr int kNoAllocParts = 4096;
+hipError_t resolve_conserved_scratch(int device, double** out);
 void launch_bead_stats(const Dev& d, int mark_offset, hipStream_t s);
 void launch_vertex_forces(const Dev& d, hipStream_t s);
 void launch_spread(const Dev& d, hipStream_t s);

@@ -97,6 +97,7 @@ struct lbm_handle {
   hipStream_t side = nullptr;      // IBM chain, forked from `stream` every step
   std::vector<hipEvent_t> step_events;  // per chunk step: bulk done, near blocks done; + one fork
   double *d_partial = nullptr, *d_out = nullptr, *d_centres = nullptr;
+  double* conserved_scratch = nullptr;  // the device's static scratch (not owned)
   std::vector<void*> allocs;
 
   Dev dev{};

@@ -23,6 +23,7 @@
 #include <hip/hip_ext.h>
 
 #include <algorithm>
+#include <mutex>
 
 namespace lbmib {
 
@@ -506,15 +507,20 @@ __global__ __launch_bounds__(kScBlock) void k_conserved_partial(Dev d, int box, 
     for (int k = 0; k < 4; ++k) part[4 * blockIdx.x + k] = v[k];
 }
 
-// Stage 2: one block folds the partials in a fixed order.
+// Stage 2: one block folds the partials in a fixed order; `mass0` (the sum
+// of the weights, one per node, or 0 when the caller adds it) is added to the
+// mass sum last.
 __global__ __launch_bounds__(kScBlock) void k_conserved_final(const double* __restrict__ part,
-                                                               int nparts, double* __restrict__ out) {
+                                                               int nparts, double* __restrict__ out,
+                                                               double mass0) {
   double v[4] = {0, 0, 0, 0};
   for (int i = threadIdx.x; i < nparts; i += kScBlock)
     for (int k = 0; k < 4; ++k) v[k] += part[4 * i + k];
   block_sum4(v);
-  if (threadIdx.x == 0)
-    for (int k = 0; k < 4; ++k) out[k] = v[k];
+  if (threadIdx.x == 0) {
+    out[0] = v[0] + mass0;
+    for (int k = 1; k < 4; ++k) out[k] = v[k];
+  }
 }
 
 // Plain device copy, one 16-byte vector per thread over a grid that covers
@@ -640,14 +646,41 @@ void launch_average_out(const Dev& d, int nblocks, int64_t count, float* u_out, 
 }
 
 void launch_conserved(const Dev& d, int storage, int box, double* partial, int nparts, double* out,
-                      hipStream_t s) {
+                      hipStream_t s, double mass0) {
   if (storage == kFp16)
     hipLaunchKernelGGL(k_conserved_partial<kFp16>, dim3(nparts), dim3(kScBlock), 0, s, d, box, partial);
   else if (storage == kFp32Plain)
     hipLaunchKernelGGL(k_conserved_partial<kFp32Plain>, dim3(nparts), dim3(kScBlock), 0, s, d, box, partial);
   else
     hipLaunchKernelGGL(k_conserved_partial<kFp32>, dim3(nparts), dim3(kScBlock), 0, s, d, box, partial);
-  hipLaunchKernelGGL(k_conserved_final, dim3(1), dim3(kScBlock), 0, s, partial, nparts, out);
+  hipLaunchKernelGGL(k_conserved_final, dim3(1), dim3(kScBlock), 0, s, partial, nparts, out, mass0);
+}
+
+// ---- static scratch of the allocation-free conserved sums ---------------------
+// The partial sums of lbm_batch_get_conserved_noalloc live in this array, one
+// copy per GPU for the life of the process.  In host code `scratch` names a
+// host-side stand-in, not device memory: its address on a GPU comes from
+// hipGetSymbolAddress, called once per device while that device is current.
+static __device__ __align__(256) double scratch[4 * kNoAllocParts];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mutex;
+double* scratch_addr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t resolve_conserved_scratch(int device, double** out) {
+  *out = nullptr;
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(scratch_mutex);
+  if (!scratch_addr[device]) {
+    double* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(reinterpret_cast<void**>(&p), HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    scratch_addr[device] = p;
+  }
+  *out = scratch_addr[device];
+  return hipSuccess;
 }
 
 }  // namespace lbmib

@@ -588,6 +588,9 @@ int create_boxes(const lbm_box_desc* boxes, int nboxes, const lbm_opts* opts, lb
   int rc = h->hip(hipGetDevice(&h->device), "hipGetDevice");
   if (!rc) rc = h->hip(hipDeviceGetAttribute(&h->ncu, hipDeviceAttributeMultiprocessorCount, h->device),
                       "hipDeviceGetAttribute");
+  // device address of the static scratch of the allocation-free conserved
+  // sums, looked up once per device while it is current
+  if (!rc) rc = h->hip(resolve_conserved_scratch(h->device, &h->conserved_scratch), "hipGetSymbolAddress");
   if (rc) {
     delete h;
     return rc;
@@ -1039,7 +1042,7 @@ int lbm_get_conserved(lbm_handle* h, double out[4]) { return lbm_batch_get_conse
 int lbm_batch_get_conserved(lbm_handle* h, int32_t box, double out[4]) {
   if (!h || !out) return LBM_EINVAL;
   if (box < -1 || box >= (int)h->boxes.size()) return h->fail(LBM_EINVAL, "box index out of range");
-  launch_conserved(h->dev, h->storage, box, h->d_partial, kReduceParts, h->d_out, h->stream);
+  launch_conserved(h->dev, h->storage, box, h->d_partial, kReduceParts, h->d_out, h->stream, 0.0);
   int rc = h->hip(hipMemcpyAsync(out, h->d_out, sizeof(double) * 4, hipMemcpyDeviceToHost, h->stream),
                   "hipMemcpyAsync");
   if (!rc) rc = h->hip(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
@@ -1048,6 +1051,17 @@ int lbm_batch_get_conserved(lbm_handle* h, int32_t box, double out[4]) {
   for (int k = 0; k < 4; ++k)
     if (!std::isfinite(out[k])) return h->fail(LBM_ENONFINITE, "non-finite mass or momentum");
   return LBM_OK;
+}
+
+int lbm_batch_get_conserved_noalloc(lbm_handle* h, int32_t box, int32_t parts, double* dst) {
+  if (!h || !dst) return LBM_EINVAL;
+  if (box < -1 || box >= (int)h->boxes.size()) return h->fail(LBM_EINVAL, "box index out of range");
+  if (parts < 1 || parts > kNoAllocParts)
+    return h->fail(LBM_EINVAL, "parts must lie in 1..4096, the partial sums the static scratch holds");
+  if (!h->conserved_scratch) return h->fail(LBM_ESTATE, "static scratch address not resolved");
+  const double mass0 = (double)(box < 0 ? h->nodes : h->boxes[box].n);  // sum of the weights: one per node
+  launch_conserved(h->dev, h->storage, box, h->conserved_scratch, parts, dst, h->stream, mass0);
+  return h->hip(hipGetLastError(), "conserved-sum launch");
 }
 
 int lbm_set_populations(lbm_handle* h, const double* dev) {

@@ -30,7 +30,8 @@ SYMBOLS = [
     "lbm_save", "lbm_load", "lbm_set_kernel_timing", "lbm_kernel_time", "lbm_bytes_per_step",
     "lbm_probe_copy_bandwidth", "lbm_set_stream_collide_launch",
     "lbm_batch_create", "lbm_batch_swimmer_add", "lbm_n_boxes", "lbm_batch_get_velocity",
-    "lbm_batch_get_conserved", "lbm_autotune", "lbm_swimmer_set_params", "lbm_adjoint",
+    "lbm_batch_get_conserved", "lbm_batch_get_conserved_noalloc", "lbm_autotune",
+    "lbm_swimmer_set_params", "lbm_adjoint",
     "lbm_strerror", "lbm_last_error",
 ]
 
@@ -131,6 +132,7 @@ def load_library():
         "lbm_n_boxes": (i32, [vp]),
         "lbm_batch_get_velocity": (C.c_int, [vp, i32, fp, C.c_int]),
         "lbm_batch_get_conserved": (C.c_int, [vp, i32, dp]),
+        "lbm_batch_get_conserved_noalloc": (C.c_int, [vp, i32, i32, dp]),
         "lbm_autotune": (C.c_int, [vp, i32, C.c_char_p, C.c_char_p, i32]),
         "lbm_swimmer_set_params": (C.c_int, [vp, i32, C.c_double, C.c_double, C.c_double, C.c_double]),
         "lbm_adjoint": (C.c_int, [vp, C.POINTER(AdjointDesc), C.POINTER(C.c_double), dp]),
@@ -333,6 +335,13 @@ class Lattice:
         out = np.zeros(4)
         self._check(self.lib.lbm_get_conserved(self.h, _ptr(out)))
         return out
+
+    def conserved_noalloc(self, dst, box=-1, parts=1024):
+        """Enqueue the conserved sums into ``dst`` (a float64 device tensor
+        of at least 4 elements) without allocating or synchronising."""
+        assert dst.dtype.itemsize == 8 and dst.numel() >= 4 and dst.is_cuda
+        self._check(self.lib.lbm_batch_get_conserved_noalloc(self.h, int(box), int(parts),
+                                                             C.c_void_p(dst.data_ptr())))
 
     def populations(self):
         nx, ny, nz = self.shape
