@@ -63,7 +63,10 @@ struct AdjWork {
   hipStream_t rmain = nullptr, rside = nullptr;  // recompute
   hipEvent_t ev[12] = {};  // 0-3, 8, 9: recompute; 4-7, 10, 11: reverse
   hipEvent_t rec_done[2] = {}, rev_done[2] = {}, start = nullptr;
-  std::map<int64_t, hipGraphExec_t> rgraphs, vgraphs;  // by (length, parity, set)
+  // recompute graphs by (length, set); reverse-sweep graphs by (objective
+  // swimmer, length, parity, set): the swimmer is a kernel argument of the
+  // reverse sweep's bead kernels
+  std::map<int64_t, hipGraphExec_t> rgraphs, vgraphs;
   double *lr = nullptr, *lfm = nullptr, *ltmp = nullptr, *bsum = nullptr, *grad = nullptr;
   float* lr32 = nullptr;
 
@@ -426,7 +429,8 @@ int run(lbm_handle* h, const lbm_adjoint_desc* ad, double* J, double* grad) {
     rc = h->hip(hipStreamWaitEvent(s, w.rec_done[k], 0), "hipStreamWaitEvent");
     if (rc) break;
     const Dev dv = set_view(dS, w.set[k], popn);
-    rc = enqueue_or_replay(h, w.vgraphs, 4 * (int64_t)m + 2 * (int64_t)(n0 & 1) + k, s,
+    const int64_t vkey = ((int64_t)ad->swimmer << 40) | (4 * (int64_t)m + 2 * (int64_t)(n0 & 1) + k);
+    rc = enqueue_or_replay(h, w.vgraphs, vkey, s,
                            [&] { enqueue_reverse(h, w, w.set[k], dv, a, m, (int)(n0 & 1), nblocks, s, w.side); });
     if (!rc) rc = h->hip(hipEventRecord(w.rev_done[k], s), "hipEventRecord");
   }

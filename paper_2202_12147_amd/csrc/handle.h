@@ -14,6 +14,11 @@
 namespace lbmib {
 
 constexpr int kGraphChunk = 32;  // steps per captured graph
+// Step graphs of 1, 2, 4, ..., kGraphChunk steps: a call of n steps replays
+// the chunk graph n / kGraphChunk times and the rest by its binary digits, so
+// every graph keeps the two-stream overlap of its steps.
+constexpr int kGraphLevels = 6;
+static_assert((1 << (kGraphLevels - 1)) == kGraphChunk, "graph levels end at the chunk");
 
 template <class T>
 T* dev_alloc(size_t n, int& rc) {
@@ -102,7 +107,7 @@ struct lbm_handle {
 
   Dev dev{};
   lbmib::rt::AdjWork* adj = nullptr;  // adjoint buffers, kept between calls
-  hipGraphExec_t g_chunk = nullptr, g_one = nullptr;
+  hipGraphExec_t g_steps[lbmib::kGraphLevels] = {};  // 1 << l steps each
 
   bool timing = false;
   double timed_ms = 0;

@@ -509,6 +509,15 @@ void harvest_timing(lbm_handle* h) {
   h->ev_used = 0;
 }
 
+// Drop the captured step graphs (kernel arguments or launch shapes changed);
+// the next graph-replayed call captures them again.
+void drop_graphs(lbm_handle* h) {
+  for (auto& g : h->g_steps) {
+    if (g) (void)hipGraphExecDestroy(g);
+    g = nullptr;
+  }
+}
+
 // Point the stream-collide launches at the time-average state.  Captured
 // graphs hold the previous kernel arguments, so they are dropped and
 // recaptured on the next step.
@@ -518,9 +527,7 @@ int set_average(lbm_handle* h, double* sums, int64_t t0, int every) {
   h->dev.uavg = sums;
   h->dev.avg_t0 = t0;
   h->dev.avg_every = every;
-  if (h->g_chunk) (void)hipGraphExecDestroy(h->g_chunk);
-  if (h->g_one) (void)hipGraphExecDestroy(h->g_one);
-  h->g_chunk = h->g_one = nullptr;
+  drop_graphs(h);
   return LBM_OK;
 }
 
@@ -744,8 +751,7 @@ int32_t lbm_n_boxes(const lbm_handle* h) { return h ? (int32_t)h->boxes.size() :
 int lbm_destroy(lbm_handle* h) {
   if (!h) return LBM_OK;
   if (h->stream) (void)hipStreamSynchronize(h->stream);
-  if (h->g_chunk) (void)hipGraphExecDestroy(h->g_chunk);
-  if (h->g_one) (void)hipGraphExecDestroy(h->g_one);
+  drop_graphs(h);
   for (auto e : h->ev_pool) (void)hipEventDestroy(e);
   for (auto e : h->step_events) (void)hipEventDestroy(e);
   if (h->side) (void)hipStreamDestroy(h->side);
@@ -898,24 +904,16 @@ int lbm_step(lbm_handle* h, int64_t n) {
     if (h->timing && h->ev_used > 256) harvest_timing(h);
     return h->hip(hipGetLastError(), "kernel launch");
   }
+  // every graph a call can replay is captured on the first call that steps,
+  // so no later call (of any step count) pays for a capture
+  for (int l = 0; l < kGraphLevels && n > 0; ++l)
+    if (!h->g_steps[l] && (rc = capture(h, 1 << l, &h->g_steps[l]))) return rc;
   int64_t left = n;
-  if (left >= kGraphChunk && !h->g_chunk) {
-    rc = capture(h, kGraphChunk, &h->g_chunk);
-    if (rc) return rc;
-  }
-  while (left >= kGraphChunk) {
-    rc = h->hip(hipGraphLaunch(h->g_chunk, h->stream), "hipGraphLaunch");
-    if (rc) return rc;
-    left -= kGraphChunk;
-  }
-  if (left > 0 && !h->g_one) {
-    rc = capture(h, 1, &h->g_one);
-    if (rc) return rc;
-  }
-  for (; left > 0; --left) {
-    rc = h->hip(hipGraphLaunch(h->g_one, h->stream), "hipGraphLaunch");
-    if (rc) return rc;
-  }
+  for (; left >= kGraphChunk; left -= kGraphChunk)
+    if ((rc = h->hip(hipGraphLaunch(h->g_steps[kGraphLevels - 1], h->stream), "hipGraphLaunch"))) return rc;
+  for (int l = kGraphLevels - 2; l >= 0; --l)
+    if ((left >> l) & 1)
+      if ((rc = h->hip(hipGraphLaunch(h->g_steps[l], h->stream), "hipGraphLaunch"))) return rc;
   h->host_step += n;
   return LBM_OK;
 }
@@ -932,8 +930,9 @@ int32_t lbm_n_markers(const lbm_handle* h) { return h ? h->nm : -1; }
 int32_t lbm_n_swimmers(const lbm_handle* h) { return h ? (int32_t)h->swimmers.size() : -1; }
 
 int lbm_get_bead_centres(lbm_handle* h, double* out) {
-  if (!h || !out) return LBM_EINVAL;
-  if (h->beads.empty()) return LBM_OK;
+  if (!h) return LBM_EINVAL;
+  if (h->beads.empty()) return LBM_OK;  // nothing to write (out may be null)
+  if (!out) return LBM_EINVAL;
   int rc = upload(h);
   if (rc) return rc;
   launch_bead_centres(h->dev, h->d_centres, h->stream);
@@ -946,7 +945,9 @@ int lbm_get_bead_centres(lbm_handle* h, double* out) {
 }
 
 int lbm_get_swimmer_centres(lbm_handle* h, double* out) {
-  if (!h || !out) return LBM_EINVAL;
+  if (!h) return LBM_EINVAL;
+  if (h->swimmers.empty()) return LBM_OK;  // nothing to write (out may be null)
+  if (!out) return LBM_EINVAL;
   std::vector<double> R(3 * h->beads.size());
   int rc = lbm_get_bead_centres(h, R.data());
   if (rc) return rc;
@@ -959,8 +960,9 @@ int lbm_get_swimmer_centres(lbm_handle* h, double* out) {
 }
 
 int lbm_get_markers(lbm_handle* h, double* out) {
-  if (!h || !out) return LBM_EINVAL;
-  if (h->nm == 0) return LBM_OK;
+  if (!h) return LBM_EINVAL;
+  if (h->nm == 0) return LBM_OK;  // nothing to write (out may be null)
+  if (!out) return LBM_EINVAL;
   int rc = upload(h);
   if (rc) return rc;
   std::vector<double> tmp(3 * (size_t)h->nm);
@@ -974,8 +976,9 @@ int lbm_get_markers(lbm_handle* h, double* out) {
 }
 
 static int get_marker_f32(lbm_handle* h, const float* src, double* out) {
-  if (!h || !out) return LBM_EINVAL;
-  if (h->nm == 0) return LBM_OK;
+  if (!h) return LBM_EINVAL;
+  if (h->nm == 0) return LBM_OK;  // nothing to write (out may be null)
+  if (!out) return LBM_EINVAL;
   int rc = upload(h);
   if (rc) return rc;
   std::vector<float> tmp(3 * (size_t)h->nm);
@@ -1291,9 +1294,7 @@ int lbm_set_stream_collide_launch(lbm_handle* h, int block, int xcd_remap, int r
   if (rc) return rc;
   set_near_bounds(h);
   h->need_prologue = true;
-  if (h->g_chunk) (void)hipGraphExecDestroy(h->g_chunk);
-  if (h->g_one) (void)hipGraphExecDestroy(h->g_one);
-  h->g_chunk = h->g_one = nullptr;
+  drop_graphs(h);
   return LBM_OK;
 }
 

@@ -94,6 +94,12 @@ def load_library():
     runtimes = _hip_runtimes()
     if len(runtimes) > 1:
         raise RuntimeError(f"two HIP runtimes are mapped in this process: {sorted(runtimes)}")
+    _lib = bind(lib)
+    return _lib
+
+
+def bind(lib):
+    """Declare the C signatures of every entry point on a loaded library."""
     vp, i32, i64, dp, fp = C.c_void_p, C.c_int32, C.c_int64, C.c_void_p, C.c_void_p
     sig = {
         "lbm_create": (C.c_int, [C.POINTER(Grid), C.c_double, C.c_int, C.POINTER(Opts),
@@ -143,7 +149,6 @@ def load_library():
         fn = getattr(lib, name)
         fn.restype = res
         fn.argtypes = args
-    _lib = lib
     return lib
 
 
