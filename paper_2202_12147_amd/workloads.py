@@ -125,6 +125,30 @@ def paper_box():
                                   alpha=math.pi / 2)])
 
 
+PAPER_MODULI = dict(ks=0.05, C=9.5, kb=1.25e-3, kv=1.0)
+
+
+def paper_moduli_case(adjoint=False):
+    """The paper's membrane moduli (Sec. 3: ks = 0.05, ka = 1, i.e. C = 9.5,
+    kb = 1.25e-3, kv = 1) on its radius-5 beads, refined twice (320
+    triangles, mean edge ~1.3 l.u.: the paper does not give the refinement;
+    with three refinements the explicit coupling diverges after ~1500 steps).
+    Swimmer as in the paper (rest length 36, k = 0.02, A = B = 5e-3,
+    alpha = pi/2) with the period shortened to 2000 steps so that the
+    driving acts within a short comparison; 112x48x48 box, tau 1, Guo,
+    3-point kernel.  adjoint=True: a 48x32x32 box, rest length 12,
+    alpha = pi/3 (a gradient case small enough for the gradient oracle)."""
+    if adjoint:
+        return dict(name="paper moduli, adjoint 48x32x32", shape=(48, 32, 32), tau=1.0, forcing=GUO,
+                    width=3, steps=2000, checkpoint=100,
+                    swimmers=[swimmer((24, 16, 16), 12.0, radius=5.0, level=2, k=0.02, A=5e-3, T=2000.0,
+                                      alpha=math.pi / 3, **PAPER_MODULI)])
+    return dict(name="paper moduli 112x48x48", shape=(112, 48, 48), tau=1.0, forcing=GUO, width=3,
+                steps=200,
+                swimmers=[swimmer((56, 24, 24), 36.0, radius=5.0, level=2, k=0.02, A=5e-3, T=2000.0,
+                                  **PAPER_MODULI)])
+
+
 def random_deviation(shape, seed=0, eps=1e-4, modes=3):
     """Smooth random population deviations [19, z, y, x]: a few random Fourier
     modes per population, amplitude ``eps``."""

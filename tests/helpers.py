@@ -23,3 +23,11 @@ def gpu_available():
         return torch.cuda.is_available()
     except Exception:
         return False
+
+
+def max_rel(a, b):
+    """Element-wise error of a against b, relative to the largest |b|:
+    max |a - b| / max |b|."""
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))

@@ -18,7 +18,7 @@ import pytest
 import bench
 from oracle import orc
 from paper_2202_12147_amd import lbmib, workloads as wl
-from tests.helpers import oracle_from, rel_l2
+from tests.helpers import max_rel, oracle_from, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -121,8 +121,9 @@ def test_fp16_launch_shapes_bitwise_equal_with_swimmer(block, remap, resident):
 def test_fp16_above_the_write_through_size():
     # 256^3 with FP16 storage holds 1.27 GB of populations, above the 1 GiB
     # up to which stores are written through: the large-set store path of
-    # FP16 against the oracle over ten steps (one-step bars: velocity 2e-3;
-    # markers move ~2.5e-5 per step with a 5e-4 relative FP16 error)
+    # FP16 against the oracle over ten steps (measured: velocity rel-L2
+    # 1.0e-4, element-wise 1.3e-4 of max |u|; bars three times that; markers
+    # move ~2.5e-5 per step with a 5e-4 relative FP16 error)
     case = wl.small_case()
     case["shape"] = (256, 256, 256)
     case["swimmers"] = [wl.swimmer((128, 128, 128), 10.0, A=1e-3, T=500.0, phi0=1.0)]
@@ -131,6 +132,7 @@ def test_fp16_above_the_write_through_size():
     o.step(10)
     lat.step(10)
     du = rel_l2(lat.velocity(), o.velocity())
+    dmax = max_rel(lat.velocity(), o.velocity())
     dr = np.abs(lat.markers() - o.markers()).max()
-    print("fp16 256^3: u rel-L2", du, "max |dr|", dr, flush=True)
-    assert du < 2e-3 and dr < 1e-6
+    print("fp16 256^3: u rel-L2", du, "max-rel", dmax, "max |dr|", dr, flush=True)
+    assert du < 3e-4 and dmax < 4e-4 and dr < 1e-6

@@ -9,16 +9,19 @@ integrate the FP32 interpolated velocity, whose error is at most ~4e-6 of the
 fastest marker speed (~2.5e-5 l.u./step), so positions may drift apart by
 POS_PER_STEP = 1e-10 l.u. per step; swimmer displacement rel <= 1e-3 over 1000
 steps (the displacement is ~1e-4 l.u., a small difference of FP64 centres)."""
+import os
+
 import numpy as np
 import pytest
 
 import bench
 from paper_2202_12147_amd import lbmib, workloads as wl
-from tests.helpers import oracle_from, rel_l2
+from tests.helpers import max_rel, oracle_from, rel_l2
 
 pytestmark = pytest.mark.gpu
 
 POS_PER_STEP = 1e-10
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 
 def _run_pair(case, steps, storage=lbmib.FP32_SHIFTED, launch=None):
@@ -47,9 +50,10 @@ def test_small_case_200_steps(width, forcing):
     print("case", width, forcing, steps, flush=True)
     o, lat = _run_pair(case, steps)
     du = rel_l2(lat.velocity(), o.velocity())
+    dmax = max_rel(lat.velocity(), o.velocity())
     dr = np.abs(lat.markers() - o.markers()).max()
-    print("rel-L2 u", du, "max |dr|", dr, flush=True)
-    assert du < 1e-5
+    print("rel-L2 u", du, "max-rel u", dmax, "max |dr|", dr, flush=True)
+    assert du < 1e-5 and dmax < 1e-5
     assert dr < POS_PER_STEP * steps
     np.testing.assert_allclose(lat.bead_centres(), o.bead_centres(), rtol=0,
                                atol=POS_PER_STEP * steps)
@@ -78,14 +82,48 @@ def test_small_case_full_run():
     assert np.abs(c[1:]).max() < 1e-6
 
 
-def test_single_128_parity_few_steps():
+def test_single_128_parity_200_steps():
     # the 128^3, 4-point, 1280-triangle workload at full size, in the launch
-    # configuration the benchmark times (its 32-step graph replayed once, then
-    # eight steps more)
+    # configuration the benchmark times (its 32-step graph replayed six
+    # times, then the 8-step graph): the whole field element by element
     case = wl.single_128(seed=0)
-    o, lat = _run_pair(case, 40, launch=bench.MAIN_LAUNCH)
-    assert rel_l2(lat.velocity(), o.velocity()) < 1e-5
-    assert np.abs(lat.markers() - o.markers()).max() < POS_PER_STEP * 40
+    o, lat = _run_pair(case, 200, launch=bench.MAIN_LAUNCH)
+    u, uo = lat.velocity(), o.velocity()
+    du, dmax = rel_l2(u, uo), max_rel(u, uo)
+    dr = np.abs(lat.markers() - o.markers()).max()
+    print(f"128^3 200 steps: u rel-L2 {du:.2e} max-rel {dmax:.2e} markers {dr:.2e}", flush=True)
+    assert du < 1e-5 and dmax < 1e-5
+    assert dr < POS_PER_STEP * 200
+    np.testing.assert_allclose(lat.bead_centres(), o.bead_centres(), rtol=0, atol=POS_PER_STEP * 200)
+
+
+def test_single_128_first_period_trajectory():
+    """Swimmer centre X(n) over the first actuation period (2000 steps) of the
+    128^3 workload in the benchmark's launch configuration, against the FP64
+    oracle's trajectory stored by tests/golden/make_trajectory_golden.py,
+    read after every 32-step graph: X within POS_PER_STEP per step, the
+    displacement X(n) - X(0) within 1e-3 of the oracle's largest one."""
+    ref = np.loadtxt(os.path.join(GOLDEN, "single128_x_2000.txt"))
+    case = wl.single_128(seed=0)
+    lat = lbmib.from_workload(case)
+    lat.set_stream_collide_launch(*bench.MAIN_LAUNCH)
+    X0 = lat.swimmer_centres()[0]
+    np.testing.assert_allclose(X0, ref[0, 1:], rtol=0, atol=1e-12)
+    worst = worst_disp = 0.0
+    dmax = np.abs(ref[:, 1:] - ref[0, 1:]).max()
+    n = 0
+    while n < 2000:
+        k = min(32, 2000 - n)
+        lat.step(k)
+        n += k
+        X = lat.swimmer_centres()[0]
+        err = np.abs(X - ref[n, 1:]).max()
+        worst = max(worst, err)
+        worst_disp = max(worst_disp, np.abs((X - X0) - (ref[n, 1:] - ref[0, 1:])).max() / dmax)
+        assert err < POS_PER_STEP * n, (n, X, ref[n])
+    print(f"first period: max |X - X_ref| {worst:.2e}, displacement error {worst_disp:.2e} of "
+          f"max |X - X0| = {dmax:.3e}", flush=True)
+    assert worst_disp < 1e-3
 
 
 def test_paper_box_parity_few_steps():
@@ -168,9 +206,10 @@ def test_swimmer_across_periodic_seams(width):
     print("seam case", width, steps, flush=True)
     o, lat = _run_pair(case, steps)
     du = rel_l2(lat.velocity(), o.velocity())
+    dmax = max_rel(lat.velocity(), o.velocity())
     dr = np.abs(lat.markers() - o.markers()).max()
-    print("rel-L2 u", du, "max |dr|", dr, flush=True)
-    assert du < 1e-5
+    print("rel-L2 u", du, "max-rel u", dmax, "max |dr|", dr, flush=True)
+    assert du < 1e-5 and dmax < 1e-5
     assert dr < POS_PER_STEP * steps
     np.testing.assert_allclose(lat.swimmer_centres(), o.swimmer_centres(), rtol=0, atol=POS_PER_STEP * steps)
 
@@ -191,9 +230,10 @@ def test_swimmer_across_seams_of_ragged_box(offset):
     print("ragged seam case", offset, steps, flush=True)
     o, lat = _run_pair(case, steps)
     du = rel_l2(lat.velocity(), o.velocity())
+    dmax = max_rel(lat.velocity(), o.velocity())
     dr = np.abs(lat.markers() - o.markers()).max()
-    print("rel-L2 u", du, "max |dr|", dr, flush=True)
-    assert du < 1e-5
+    print("rel-L2 u", du, "max-rel u", dmax, "max |dr|", dr, flush=True)
+    assert du < 1e-5 and dmax < 1e-5
     assert dr < POS_PER_STEP * steps
     np.testing.assert_allclose(lat.swimmer_centres(), o.swimmer_centres(), rtol=0, atol=POS_PER_STEP * steps)
 
@@ -254,3 +294,24 @@ def test_without_actuation_the_swimmer_stays_put():
     print("max |dr|", dr, "max |u|", umax, "oracle max |dr|", np.abs(o.markers() - r0).max(), flush=True)
     assert dr < 1e-12 and umax < 1e-12
     assert np.abs(o.markers() - r0).max() < 1e-12
+
+
+def test_any_step_count_split_gives_the_same_bits():
+    """lbm_step(n) replays the 32-step graph n // 32 times and one graph per
+    binary digit of the rest (16, 8, 4, 2, 1 steps), each keeping the
+    two-stream order: every split of the same 71 steps, and direct launches,
+    end in the same bits."""
+    case = wl.small_case()
+    runs = {"direct": (lbmib.from_workload(case, use_graphs=False), [71]),
+            "one call": (lbmib.from_workload(case), [71]),
+            "singles": (lbmib.from_workload(case), [1] * 71),
+            "mixed": (lbmib.from_workload(case), [5, 20, 13, 32, 1])}
+    for name, (lat, calls) in runs.items():
+        for c in calls:
+            lat.step(c)
+        lat.sync()
+        assert lat.time == 71, name
+    ref = runs["direct"][0]
+    for name, (lat, _) in runs.items():
+        assert np.array_equal(lat.markers(), ref.markers()), name
+        assert np.array_equal(lat.populations(), ref.populations()), name
