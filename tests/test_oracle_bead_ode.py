@@ -1,0 +1,94 @@
+"""Pins of the paper's analytical comparison model (oracle/bead_ode.py,
+Sec. 2.4 and Eq. fit-eq): no forcing, no motion; a mirror-symmetric stroke
+cannot move the centre; the far-field swimming speed of the three-sphere
+swimmer, V = 7a/(24 L^2) <u1 u2' - u2 u1'> (derived in the module header
+from the Oseen interactions at first order in a/L); the speed is quadratic
+in the driving amplitudes; fourth-order time stepping; a zero delay is no
+delay."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import bead_ode
+from paper_2202_12147_amd import workloads as wl
+
+
+def _swimmer(**kw):
+    p = dict(radius=0.25, k=0.05, A=1e-5, T=400.0, alpha=math.pi / 2)
+    p.update(kw)
+    return wl.swimmer((0.0, 0.0, 0.0), p.pop("L", 50.0), **p)
+
+
+def test_no_forcing_no_motion():
+    m = bead_ode.BeadSwimmers([_swimmer(A=0.0, B=0.0)], mu=1.0 / 6.0)
+    R0 = m.R.copy()
+    m.run(800, dt=2.0)
+    assert np.abs(m.R - R0).max() == 0.0
+
+
+@pytest.mark.parametrize("tensor", ["oseen", "rotne_prager"])
+def test_mirror_symmetric_stroke_does_not_swim(tensor):
+    # B = -A, alpha = 0: the outer beads are pushed apart and together
+    # symmetrically; the configuration stays mirror symmetric about the
+    # middle bead, so the centre cannot move
+    m = bead_ode.BeadSwimmers([_swimmer(A=2e-3, B=-2e-3, alpha=0.0, radius=2.0)], mu=1.0 / 6.0,
+                              tensor=tensor)
+    X = m.run(1200, dt=1.0, every=100)
+    assert np.abs(X[:, 0, 0]).max() < 1e-13
+    # and the arms do move
+    assert abs(np.linalg.norm(m.R[0] - m.R[1]) - 50.0) > 1e-4
+
+
+@pytest.mark.parametrize("tensor", ["oseen", "rotne_prager"])
+def test_far_field_swimming_speed(tensor):
+    """a/L = 0.005, arm changes ~1e-3 of L: the speed over one period matches
+    7a/(24 L^2) <u1 u2' - u2 u1'> evaluated on the model's own arm
+    trajectories (the loop integral by the shoelace sum over the sampled
+    closed arm cycle) to the O(a/L) of the expansion."""
+    a, L, T, dt = 0.25, 50.0, 400.0, 0.5
+    m = bead_ode.BeadSwimmers([_swimmer(A=2.5e-3)], mu=1.0 / 6.0, tensor=tensor)
+    m.run(int(3 * T / dt), dt)  # transient
+    n = int(T / dt)
+    R = np.concatenate([m.R[None].copy(), m.run(n, dt, every=1, beads=True)])
+    u1 = R[:, 1, 0] - R[:, 0, 0] - L
+    u2 = R[:, 2, 0] - R[:, 1, 0] - L
+    loop = np.sum(u1[:-1] * u2[1:] - u2[:-1] * u1[1:])
+    pred = 7.0 * a / (24.0 * L * L) * loop / T
+    X = R.mean(1)[:, 0]
+    v = (X[-1] - X[0]) / T
+    print(tensor, "V", v, "far-field", pred, "rel", abs(v - pred) / abs(pred))
+    assert abs(v - pred) <= 0.03 * abs(pred)
+
+
+def test_quadratic_in_the_amplitudes():
+    # the arms respond linearly to the driving forces (with a relaxation lag,
+    # so A^2 and B^2 terms appear beside A B), and the speed is the loop area
+    # of the arm cycle: doubling both amplitudes quadruples the speed up to
+    # the O(u/L) nonlinearity
+    def speed(A, B):
+        m = bead_ode.BeadSwimmers([_swimmer(A=A, B=B)], mu=1.0 / 6.0)
+        return bead_ode.period_velocity(m, 400.0, 4, dt=1.0)[-1, 0]
+
+    v1, v2 = speed(5e-4, 3e-4), speed(1e-3, 6e-4)
+    print("speeds", v1, v2)
+    assert abs(v2 / v1 - 4.0) < 5e-3
+
+
+def test_time_stepping_is_fourth_order():
+    def end(dt):
+        m = bead_ode.BeadSwimmers([_swimmer(A=2e-3, radius=2.0, T=200.0)], mu=1.0 / 6.0)
+        m.run(int(400 / dt), dt)
+        return m.R.copy()
+
+    e1 = np.abs(end(4.0) - end(1.0)).max()
+    e2 = np.abs(end(2.0) - end(1.0)).max()
+    assert e2 < e1 / 8.0  # error ratio ~ (4^4 - 1)/(2^4 - 1) = 17 for fourth order
+
+
+def test_zero_delay_equals_no_delay():
+    a = bead_ode.BeadSwimmers([_swimmer(A=2e-3, radius=2.0)], mu=1.0 / 6.0, delay=0.0)
+    b = bead_ode.BeadSwimmers([_swimmer(A=2e-3, radius=2.0)], mu=1.0 / 6.0, delay=1e-12)
+    a.run(300, 1.0)
+    b.run(300, 1.0)
+    np.testing.assert_allclose(a.R, b.R, rtol=0, atol=1e-9)
