@@ -177,7 +177,10 @@ struct Dev {
   const int* tile_box;   // tile -> box (batches only)
   int* overflow;         // set when a bead region outgrows its reserved tiles
   int spread_blocks;
-  const int* spread_bead;  // spread block -> bead
+  // per spread block (one per reserved tile of each bead), two int4:
+  // {bead, box, first bead of the box, beads in the box}, {kx, ky, kz, 0}
+  // the tile's offset within the bead's reserved tiles
+  const int4* spread_info;
   // (rho, u) of every node, written by the moment-recording stream-collide
   // variant only (segment recompute of the adjoint)
   float4* mom;

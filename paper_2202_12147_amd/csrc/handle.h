@@ -95,7 +95,7 @@ struct lbm_handle {
   float *d_G0inv = nullptr, *d_A0 = nullptr, *d_idet = nullptr;
   int *d_lane_elem = nullptr, *d_lane_v = nullptr;
   int* d_overflow = nullptr;
-  int* d_spread_bead = nullptr;
+  int* d_spread_info = nullptr;  // [spread block][8], see Dev::spread_info
   int *d_near = nullptr, *d_near_list = nullptr, *d_near_count = nullptr;
   int* d_work = nullptr;           // persistent bulk block counters (kWorkCounters)
   bool need_prologue = true;

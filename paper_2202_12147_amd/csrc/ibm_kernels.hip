@@ -47,6 +47,10 @@ constexpr int kSpreadBlock = 256;
 constexpr int kSpreadBlockWide = 512;
 constexpr int kWideBeads = 32;  // at most this many beads: wide workgroups
 constexpr int kInterpBlock = 256;
+// Bead statistics: meshes of up to this many nodes (four refinements) are
+// staged in LDS for the volume sum; triangle ids loaded per round trip.
+constexpr int kStatsLdsVerts = 2562;
+constexpr int kStatsTriRounds = 5;
 
 __device__ inline int pmod(int a, int b) {
   int r = a % b;
@@ -139,6 +143,7 @@ __global__ __launch_bounds__(BS) void k_bead_stats(Dev d, int mark_offset) {
   constexpr int NV = 10;  // sums x y z, min x y z, max x y z, volume
   __shared__ double part[NWAVE][NV];
   __shared__ int reg_lo[3], reg_hi[3];
+  __shared__ double lpos[3][kStatsLdsVerts];
   const int b = blockIdx.x;
   const Bead Bd = d.beads[b];
   const Box Bx = d.boxes[Bd.box];
@@ -149,8 +154,19 @@ __global__ __launch_bounds__(BS) void k_bead_stats(Dev d, int mark_offset) {
   const BeadState* prev = d.bstate_prev ? d.bstate_prev : d.bstate;
   const double cx = prev[b].c[0], cy = prev[b].c[1], cz = prev[b].c[2];
   double v[NV] = {0, 0, 0, 1e300, 1e300, 1e300, -1e300, -1e300, -1e300, 0};
+  // The node positions are loaded once and, for meshes of up to
+  // kStatsLdsVerts nodes, staged in LDS, where the volume sum reads the
+  // triangle corners; the triangles' corner ids are loaded with the
+  // positions, so the kernel makes one round trip to memory for its inputs
+  // (it runs beside the bulk stream-collide launch, where trips are slow).
+  const bool staged = Bd.nv <= kStatsLdsVerts;
   for (int i = threadIdx.x; i < Bd.nv; i += BS) {
     const double3 p = load_pos(d.pos, d.nm, Bd.first + i);
+    if (staged) {
+      lpos[0][i] = p.x;
+      lpos[1][i] = p.y;
+      lpos[2][i] = p.z;
+    }
     v[0] += p.x;
     v[1] += p.y;
     v[2] += p.z;
@@ -161,15 +177,39 @@ __global__ __launch_bounds__(BS) void k_bead_stats(Dev d, int mark_offset) {
     v[7] = fmax(v[7], p.y);
     v[8] = fmax(v[8], p.z);
   }
-  for (int t = threadIdx.x; t < Bd.ntri; t += BS) {
-    const int tt = Bd.tri0 + t;
-    const double3 p0 = load_pos(d.pos, d.nm, d.tri[tt]);
-    const double3 p1 = load_pos(d.pos, d.nm, d.tri[d.ntri + tt]);
-    const double3 p2 = load_pos(d.pos, d.nm, d.tri[2 * d.ntri + tt]);
-    const double ax = p0.x - cx, ay = p0.y - cy, az = p0.z - cz;
-    const double bx = p1.x - cx, by = p1.y - cy, bz = p1.z - cz;
-    const double qx = p2.x - cx, qy = p2.y - cy, qz = p2.z - cz;
-    v[9] += ax * (by * qz - bz * qy) + ay * (bz * qx - bx * qz) + az * (bx * qy - by * qx);
+  for (int t0 = 0; t0 < Bd.ntri; t0 += kStatsTriRounds * BS) {
+    int ids[kStatsTriRounds][3];
+#pragma unroll
+    for (int r = 0; r < kStatsTriRounds; ++r) {
+      const int t = t0 + r * BS + (int)threadIdx.x;
+      const int tt = Bd.tri0 + t;
+      ids[r][0] = ids[r][1] = ids[r][2] = -1;
+      if (t < Bd.ntri) {
+        ids[r][0] = d.tri[tt];
+        ids[r][1] = d.tri[d.ntri + tt];
+        ids[r][2] = d.tri[2 * d.ntri + tt];
+      }
+    }
+    if (staged) __syncthreads();  // positions staged (uniform: staged depends on the bead only)
+#pragma unroll
+    for (int r = 0; r < kStatsTriRounds; ++r) {
+      if (ids[r][0] < 0) continue;
+      double3 p0, p1, p2;
+      if (staged) {
+        const int i0 = ids[r][0] - Bd.first, i1 = ids[r][1] - Bd.first, i2 = ids[r][2] - Bd.first;
+        p0 = make_double3(lpos[0][i0], lpos[1][i0], lpos[2][i0]);
+        p1 = make_double3(lpos[0][i1], lpos[1][i1], lpos[2][i1]);
+        p2 = make_double3(lpos[0][i2], lpos[1][i2], lpos[2][i2]);
+      } else {
+        p0 = load_pos(d.pos, d.nm, ids[r][0]);
+        p1 = load_pos(d.pos, d.nm, ids[r][1]);
+        p2 = load_pos(d.pos, d.nm, ids[r][2]);
+      }
+      const double ax = p0.x - cx, ay = p0.y - cy, az = p0.z - cz;
+      const double bx = p1.x - cx, by = p1.y - cy, bz = p1.z - cz;
+      const double qx = p2.x - cx, qy = p2.y - cy, qz = p2.z - cz;
+      v[9] += ax * (by * qz - bz * qy) + ay * (bz * qx - bx * qz) + az * (bx * qy - by * qx);
+    }
   }
 #pragma unroll
   for (int s = 32; s > 0; s >>= 1) {
@@ -426,10 +466,6 @@ __global__ __launch_bounds__(256) void k_vertex_forces(Dev d) {
 }
 
 // ---- spreading --------------------------------------------------------------------
-__device__ inline bool covers(const BeadState& s, int tx, int ty, int tz, const Box& B) {
-  return pmod(tx - s.tlo[0], B.tx) < s.tcnt[0] && pmod(ty - s.tlo[1], B.ty) < s.tcnt[1] &&
-         pmod(tz - s.tlo[2], B.tz) < s.tcnt[2];
-}
 
 // Offset of a marker's stencil from the tile origin, taking the periodic image
 // that meets the tile; returns false when no image meets it.
@@ -453,8 +489,14 @@ __device__ inline bool stencil_offset(int base, int origin, int extent, int N, i
 // goes to wavefront e % W (W wavefronts per workgroup), which adds the
 // marker's stencil (one lane per stencil node, all distinct) into the
 // wavefront's private LDS copy of the tile; the W copies are summed in
-// wavefront order.  No atomics, fixed
-// summation order: deterministic.
+// wavefront order.  No atomics, fixed summation order: deterministic.
+//
+// The kernel runs beside the bulk stream-collide launch, where every
+// dependent trip to memory is slow, so its loads are issued in three rounds:
+// the block's table entry; the box and the tile regions and mesh ranges of
+// all the box's beads (into LDS); then the positions and forces of every
+// marker of the beads covering the tile, held in registers (kSpreadRounds
+// chunks of BS markers per round trip) while the chunks are staged.
 template <int NW>
 struct SpreadEntry {
   int off;           // packed stencil offset from the tile origin, +8 per axis
@@ -462,23 +504,51 @@ struct SpreadEntry {
   float f[3];        // marker force
 };
 
+constexpr int kSpreadBeads = 64;   // beads per box held in LDS (more: read from memory)
+constexpr int kSpreadRounds = 4;   // marker chunks loaded per round trip
+
+// Tile region and mesh range of bead i of the box (LDS copy or memory).
+struct SpreadBead {
+  int tlo[3], tcnt[3], first, nv;
+};
+
+__device__ inline SpreadBead spread_bead(const Dev& d, const SpreadBead* sb, int bead0, int nb, int i) {
+  if (nb <= kSpreadBeads) return sb[i];
+  const BeadState& s = d.bstate[bead0 + i];
+  const Bead& q = d.beads[bead0 + i];
+  return SpreadBead{{s.tlo[0], s.tlo[1], s.tlo[2]}, {s.tcnt[0], s.tcnt[1], s.tcnt[2]}, q.first, q.nv};
+}
+
+__device__ inline bool covers(const SpreadBead& s, int tx, int ty, int tz, const Box& B) {
+  return pmod(tx - s.tlo[0], B.tx) < s.tcnt[0] && pmod(ty - s.tlo[1], B.ty) < s.tcnt[1] &&
+         pmod(tz - s.tlo[2], B.tz) < s.tcnt[2];
+}
+
 template <int NW, int BS>
 __global__ __launch_bounds__(BS) void k_spread(Dev d) {
   constexpr int kSpreadWaves = BS / 64;
   __shared__ float acc[kSpreadWaves][3][kTileNodes];
   __shared__ SpreadEntry<NW> ent[BS];
   __shared__ int wave_cnt[kSpreadWaves];
-  const int blk = blockIdx.x;
-  const int b = d.spread_bead[blk];
-  const Bead Bd = d.beads[b];
-  const BeadState S = d.bstate[b];
-  const int k = blk - Bd.tile_block0;
-  const int kx = k % Bd.tiles_x, ky = (k / Bd.tiles_x) % Bd.tiles_y, kz = k / (Bd.tiles_x * Bd.tiles_y);
-  if (kx >= S.tcnt[0] || ky >= S.tcnt[1] || kz >= S.tcnt[2]) return;
-  const Box B = d.boxes[Bd.box];
-  const int tx = pmod(S.tlo[0] + kx, B.tx), ty = pmod(S.tlo[1] + ky, B.ty), tz = pmod(S.tlo[2] + kz, B.tz);
-  for (int b2 = B.bead0; b2 < b; ++b2)
-    if (covers(d.bstate[b2], tx, ty, tz, B)) return;  // an earlier bead owns this tile
+  __shared__ SpreadBead sb[kSpreadBeads];
+  // round trip 1: the block's bead, box and candidate tile within the bead
+  const int4 info = d.spread_info[2 * blockIdx.x];
+  const int4 kk = d.spread_info[2 * blockIdx.x + 1];
+  const int b = info.x, bead0 = info.z, nb = info.w, own = b - bead0;
+  // round trip 2: the box and every bead of the box
+  const Box B = d.boxes[info.y];
+  if (nb <= kSpreadBeads)
+    for (int i = threadIdx.x; i < nb; i += BS) {
+      const BeadState& st = d.bstate[bead0 + i];
+      const Bead& q = d.beads[bead0 + i];
+      sb[i] = SpreadBead{{st.tlo[0], st.tlo[1], st.tlo[2]}, {st.tcnt[0], st.tcnt[1], st.tcnt[2]}, q.first, q.nv};
+    }
+  __syncthreads();
+  const SpreadBead S = spread_bead(d, sb, bead0, nb, own);
+  if (kk.x >= S.tcnt[0] || kk.y >= S.tcnt[1] || kk.z >= S.tcnt[2]) return;
+  const int tx = pmod(S.tlo[0] + kk.x, B.tx), ty = pmod(S.tlo[1] + kk.y, B.ty), tz = pmod(S.tlo[2] + kk.z, B.tz);
+  for (int i = 0; i < own; ++i)
+    if (covers(spread_bead(d, sb, bead0, nb, i), tx, ty, tz, B)) return;  // an earlier bead owns this tile
   const int64_t n = *d.step + d.sub;
   const int ox = tx * kTile, oy = ty * kTile, oz = tz * kTile;
   const int ex = min(kTile, B.nx - ox), ey = min(kTile, B.ny - oy), ez = min(kTile, B.nz - oz);
@@ -490,26 +560,55 @@ __global__ __launch_bounds__(BS) void k_spread(Dev d) {
       acc[w][2][nd] = 0.0f;
     }
   // stencil node of this lane (NW^3 <= 64 lanes used)
-  const int sa = lane % NW, sb = (lane / NW) % NW, sc = lane / (NW * NW);
-  for (int b2 = b; b2 < B.bead0 + B.nbeads; ++b2) {
-    if (b2 != b && !covers(d.bstate[b2], tx, ty, tz, B)) continue;
-    const Bead Q = d.beads[b2];
-    for (int c0 = 0; c0 < Q.nv; c0 += BS) {
+  const int sa = lane % NW, sb_ = (lane / NW) % NW, sc = lane / (NW * NW);
+  // chunks (covering bead, first marker) in order: this bead, then the later
+  // beads of the box that cover the tile; kSpreadRounds chunks per load round
+  int cb = own, c0 = 0;  // next chunk to load
+  SpreadBead Q = S;
+  while (cb < nb) {
+    double px[kSpreadRounds], py[kSpreadRounds], pz[kSpreadRounds];
+    float fx[kSpreadRounds], fy[kSpreadRounds], fz[kSpreadRounds];
+    int nvr[kSpreadRounds];  // markers of each loaded chunk's bead left from its first (0: no chunk)
+    int nr = 0;
+#pragma unroll
+    for (int r = 0; r < kSpreadRounds; ++r) {
+      nvr[r] = 0;
+      px[r] = py[r] = pz[r] = 0.0;
+      fx[r] = fy[r] = fz[r] = 0.0f;
+      if (cb >= nb) continue;
       const int i = c0 + (int)threadIdx.x;
-      bool take = false;
-      int offx = 0, offy = 0, offz = 0;
-      double3 p = make_double3(0, 0, 0);
-      float fmx = 0, fmy = 0, fmz = 0;
-      int bx = 0, by = 0, bz = 0;
+      nvr[r] = Q.nv - c0;
       if (i < Q.nv) {
         const int m = Q.first + i;
-        p = load_pos(d.pos, d.nm, m);
-        fmx = d.fm[m];
-        fmy = d.fm[d.nm + m];
-        fmz = d.fm[2 * d.nm + m];
-        bx = stencil_base<NW>(p.x);
-        by = stencil_base<NW>(p.y);
-        bz = stencil_base<NW>(p.z);
+        px[r] = d.pos[m];
+        py[r] = d.pos[d.nm + m];
+        pz[r] = d.pos[2 * d.nm + m];
+        fx[r] = d.fm[m];
+        fy[r] = d.fm[d.nm + m];
+        fz[r] = d.fm[2 * d.nm + m];
+      }
+      ++nr;
+      // advance to the next chunk: the rest of this bead, else the next
+      // later bead that covers the tile
+      c0 += BS;
+      if (c0 >= Q.nv) {
+        c0 = 0;
+        for (++cb; cb < nb; ++cb) {
+          Q = spread_bead(d, sb, bead0, nb, cb);
+          if (covers(Q, tx, ty, tz, B)) break;
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < kSpreadRounds; ++r) {
+      if (r >= nr) break;
+      bool take = false;
+      int offx = 0, offy = 0, offz = 0;
+      int bx = 0, by = 0, bz = 0;
+      if ((int)threadIdx.x < nvr[r]) {
+        bx = stencil_base<NW>(px[r]);
+        by = stencil_base<NW>(py[r]);
+        bz = stencil_base<NW>(pz[r]);
         take = stencil_offset<NW>(bx, ox, ex, B.nx, offx) && stencil_offset<NW>(by, oy, ey, B.ny, offy) &&
                stencil_offset<NW>(bz, oz, ez, B.nz, offz);
       }
@@ -528,23 +627,23 @@ __global__ __launch_bounds__(BS) void k_spread(Dev d) {
         E.off = ((offx + 8) << 10) | ((offy + 8) << 5) | (offz + 8);
 #pragma unroll
         for (int a = 0; a < NW; ++a) {
-          E.w[0][a] = phi<NW>((float)((double)(bx + a) - p.x));
-          E.w[1][a] = phi<NW>((float)((double)(by + a) - p.y));
-          E.w[2][a] = phi<NW>((float)((double)(bz + a) - p.z));
+          E.w[0][a] = phi<NW>((float)((double)(bx + a) - px[r]));
+          E.w[1][a] = phi<NW>((float)((double)(by + a) - py[r]));
+          E.w[2][a] = phi<NW>((float)((double)(bz + a) - pz[r]));
         }
-        E.f[0] = fmx;
-        E.f[1] = fmy;
-        E.f[2] = fmz;
+        E.f[0] = fx[r];
+        E.f[1] = fy[r];
+        E.f[2] = fz[r];
       }
       __syncthreads();
       if (lane < NW * NW * NW) {
         for (int e = wave; e < total; e += kSpreadWaves) {
           const SpreadEntry<NW>& E = ent[e];
           const int lx = ((E.off >> 10) & 31) - 8 + sa;
-          const int ly = ((E.off >> 5) & 31) - 8 + sb;
+          const int ly = ((E.off >> 5) & 31) - 8 + sb_;
           const int lz = (E.off & 31) - 8 + sc;
           if ((unsigned)lx < (unsigned)ex && (unsigned)ly < (unsigned)ey && (unsigned)lz < (unsigned)ez) {
-            const float w = E.w[0][sa] * E.w[1][sb] * E.w[2][sc];
+            const float w = E.w[0][sa] * E.w[1][sb_] * E.w[2][sc];
             const int node = lx + kTile * (ly + kTile * lz);
             acc[wave][0][node] += w * E.f[0];
             acc[wave][1][node] += w * E.f[1];

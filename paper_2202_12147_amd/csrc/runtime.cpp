@@ -244,15 +244,6 @@ int upload(lbm_handle* h) {
   std::vector<double> pos(3 * (size_t)nm);
   for (int m = 0; m < nm; ++m)
     for (int k = 0; k < 3; ++k) pos[(size_t)k * nm + m] = h->pos0[3 * (size_t)m + k];
-  // spread candidate blocks
-  std::vector<int> spread_bead;
-  for (size_t b = 0; b < h->beads.size(); ++b) {
-    Bead& B = h->beads[b];
-    B.tile_block0 = (int)spread_bead.size();
-    const int cnt = B.tiles_x * B.tiles_y * B.tiles_z;
-    spread_bead.insert(spread_bead.end(), cnt, (int)b);
-  }
-  h->spread_blocks = (int)spread_bead.size();
   for (Box& B : h->boxes) {
     B.bead0 = 0;
     B.nbeads = 0;
@@ -262,6 +253,21 @@ int upload(lbm_handle* h) {
     if (B.nbeads == 0) B.bead0 = (int)b;
     B.nbeads += 1;
   }
+  // spread candidate blocks, one per reserved tile of each bead: {bead, box,
+  // first bead of the box, beads of the box}, {tile offsets kx, ky, kz}
+  std::vector<int> spread_info;
+  for (size_t b = 0; b < h->beads.size(); ++b) {
+    Bead& Bd = h->beads[b];
+    const Box& B = h->boxes[Bd.box];
+    Bd.tile_block0 = (int)(spread_info.size() / 8);
+    for (int kz = 0; kz < Bd.tiles_z; ++kz)
+      for (int ky = 0; ky < Bd.tiles_y; ++ky)
+        for (int kx = 0; kx < Bd.tiles_x; ++kx) {
+          const int e[8] = {(int)b, Bd.box, B.bead0, B.nbeads, kx, ky, kz, 0};
+          spread_info.insert(spread_info.end(), e, e + 8);
+        }
+  }
+  h->spread_blocks = (int)(spread_info.size() / 8);
 
   auto put = [&](void* dst, const void* src, size_t bytes) {
     if (rc != LBM_OK || bytes == 0) return;
@@ -284,7 +290,7 @@ int upload(lbm_handle* h) {
   h->d_theta0 = h->alloc<double>(2 * h->hingeth0.size(), rc);
   h->d_lane_elem = h->alloc<int>(lane_elem.size(), rc);
   h->d_lane_v = h->alloc<int>(lane_v.size(), rc);
-  h->d_spread_bead = h->alloc<int>(spread_bead.size(), rc);
+  h->d_spread_info = h->alloc<int>(spread_info.size(), rc);
   h->d_centres = h->alloc<double>(3 * h->beads.size(), rc);
   // near-block buffers, sized for the smallest stream-collide block (128):
   // every box starts a new block, so the bound is the sum over the boxes of
@@ -334,7 +340,7 @@ int upload(lbm_handle* h) {
   }
   put(h->d_lane_elem, lane_elem.data(), sizeof(int) * lane_elem.size());
   put(h->d_lane_v, lane_v.data(), sizeof(int) * lane_v.size());
-  put(h->d_spread_bead, spread_bead.data(), sizeof(int) * spread_bead.size());
+  put(h->d_spread_info, spread_info.data(), sizeof(int) * spread_info.size());
   if (rc != LBM_OK) return rc;
 
   Dev& d = h->dev;
@@ -361,7 +367,7 @@ int upload(lbm_handle* h) {
   d.lane_elem = h->d_lane_elem;
   d.lane_v = reinterpret_cast<const int4*>(h->d_lane_v);
   d.spread_blocks = h->spread_blocks;
-  d.spread_bead = h->d_spread_bead;
+  d.spread_info = reinterpret_cast<const int4*>(h->d_spread_info);
   d.near = h->d_near;
   d.near_list = h->d_near_list;
   d.near_count = h->d_near_count;
