@@ -244,6 +244,88 @@ def paper_box_section(lbmib, wl, steps=500, warmup=50):
             "step_gbs": round(lat.bytes_per_step / (dt / steps) / 1e9, 1)}
 
 
+def kernels_section(lbmib):
+    """Full-grid stream-collide launches alone (serial launch mode, no
+    swimmer, uniform body force), FP32 and FP16-shifted storage, at 128^3
+    (populations of the order of the 256 MB last-level cache, which serves
+    part of the traffic) and at 256^3 (2.55 GB FP32, 1.27 GB FP16: HBM only):
+    mean launch duration from HIP events stamped by the dispatch packets,
+    algorithmic bytes (19 loads + 19 stores per node) per second against the
+    8 TB/s peak."""
+    out = {}
+    for name, edge, storage in (("fp32_128", 128, lbmib.FP32_SHIFTED), ("fp16_128", 128, lbmib.FP16_SHIFTED),
+                                ("fp32_256", 256, lbmib.FP32_SHIFTED), ("fp16_256", 256, lbmib.FP16_SHIFTED)):
+        lat = lbmib.Lattice((edge, edge, edge), 0.8, storage=storage, width=4, fp16_scale=2.0 ** 20)
+        lat.set_body_force((1e-6, 0.0, 0.0))
+        lat.set_stream_collide_launch(*KERNEL_LAUNCH)
+        lat.step(20)
+        lat.set_kernel_timing(True)
+        lat.step(200)
+        kms, n = lat.kernel_time()
+        lat.set_kernel_timing(False)
+        lat.sync()
+        ms = kms / max(n, 1)
+        gbs = lat.bytes_per_step / (ms * 1e-3) / 1e9
+        out[name] = {"grid": [edge] * 3, "bytes_per_launch": lat.bytes_per_step, "avg_kernel_ms": round(ms, 5),
+                     "gbs": round(gbs, 1), "frac": round(gbs / PEAK_HBM_GBS, 4), "launches": n}
+        lat.close()
+    return out
+
+
+def paper_length_section(lbmib, wl, periods, out_dir=None):
+    """The paper's single-swimmer run over `periods` actuation periods of
+    2e4 steps on the 1024x256x256 box (workloads.paper_run): the swimmer
+    velocity of each period (Eq. vel_swim), the Reynolds numbers of the
+    swimmer (v_cm * 2 L / nu) and of the fastest bead (largest bead speed
+    over the last period * 2 a / nu), and the velocity field averaged over
+    the last period (Figs. 3, 6, 9), saved downsampled when out_dir is set."""
+    import numpy as np
+    case = wl.paper_run()
+    sw = case["swimmers"][0]
+    T = int(case["period"])
+    nu = (case["tau"] - 0.5) / 3.0
+    lat = lbmib.from_workload(case)
+    lat.set_stream_collide_launch(*BOX_LAUNCH)
+    X = [lat.swimmer_centres()[0].copy()]
+    per_period, bead_speed = [], 0.0
+    t0 = time.perf_counter()
+    chunk = 500
+    for p in range(periods):
+        last = p == periods - 1
+        if last:
+            lat.average_begin(1)
+        R_prev = lat.bead_centres()
+        for _ in range(T // chunk):
+            lat.step(chunk)
+            if last:
+                R = lat.bead_centres()
+                bead_speed = max(bead_speed, float(np.abs(R - R_prev).max()) / chunk)
+                R_prev = R
+        X.append(lat.swimmer_centres()[0].copy())
+        v = (X[-1] - X[-2]) / T
+        per_period.append([float(c) for c in v])
+        print(f"paper run: period {p + 1}/{periods}: v_cm {v[0]:.6e} l.u./step "
+              f"({time.perf_counter() - t0:.0f} s)", flush=True)
+    avg, count = lat.average_velocity()
+    lat.average_begin(0)
+    L = 2.0 * float(sw["L0"][0])
+    a = float(sw["radius"][0])
+    v_last = per_period[-1][0]
+    res = {"workload": case["name"], "periods": periods, "period_steps": T,
+           "forcing": "shan-chen", "tau": case["tau"], "nu": nu,
+           "v_cm_per_period": [v[0] for v in per_period],
+           "v_cm_yz_last": per_period[-1][1:],
+           "v_ref": v_last, "Re_swim": abs(v_last) * L / nu,
+           "bead_speed_max_last_period": bead_speed, "Re_bead": bead_speed * 2.0 * a / nu,
+           "mean_field_samples": count, "mean_field_max_abs": float(np.abs(avg).max()),
+           "seconds": round(time.perf_counter() - t0, 1)}
+    if out_dir:
+        os.makedirs(out_dir, exist_ok=True)
+        np.save(os.path.join(out_dir, "paper_run_mean_u_sub4.npy"), avg[:, ::4, ::4, ::4].astype(np.float32))
+        np.save(os.path.join(out_dir, "paper_run_mean_u_midplane.npy"), avg[:, avg.shape[1] // 2].astype(np.float32))
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -252,6 +334,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="run only the adjoint section (profiling of the reverse sweep)")
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="only the full-grid stream-collide launches at 128^3 and 256^3 (counter runs)")
+    ap.add_argument("--paper-length", type=int, default=0, metavar="PERIODS",
+                    help="only the paper's single-swimmer run over PERIODS periods of 2e4 steps")
+    ap.add_argument("--paper-out", default=None, help="directory for the paper run's averaged field")
     ap.add_argument("--main-only", action="store_true",
                     help="skip the fp16, batch, adjoint and paper-box sections (counter runs)")
     args = ap.parse_args()
@@ -266,6 +353,14 @@ def main():
     torch.cuda.set_device(0)
     if args.adjoint_only:
         print(json.dumps({"adjoint": adjoint_section(lbmib, wl)}), flush=True)
+        return
+    if args.kernels_only:
+        print(json.dumps({"kernels": kernels_section(lbmib), "copy_probe_gbs": lbmib.copy_bandwidth(1 << 30, 20)}),
+              flush=True)
+        return
+    if args.paper_length:
+        print(json.dumps({"paper_length": paper_length_section(lbmib, wl, args.paper_length, args.paper_out)}),
+              flush=True)
         return
     case = wl.single_128(seed=0)
     nodes = case["shape"][0] * case["shape"][1] * case["shape"][2]
@@ -334,6 +429,7 @@ def main():
     if not args.main_only:
         import numpy as np
         gmax = float(np.abs(lat.populations()).max())
+        out["kernels"] = kernels_section(lbmib)
         out["average"] = average_section(lbmib, lat, nodes)
         out["seeds"] = seeds_section(lbmib, wl)
         out["fp16"] = fp16_section(lbmib, wl, case, args.steps, args.warmup, gmax)

@@ -374,8 +374,8 @@ class Lattice:
                                                            int(resident)))
 
     def autotune(self, steps_per_candidate=64, cache_path=None):
-        """Pick the fastest stream-collide launch shape (state is restored);
-        returns the per-candidate report lines."""
+        """The launch-shape tuner of the library, which is disabled: raises
+        LbmError (LBM_ESTATE)."""
         buf = C.create_string_buffer(4096)
         cp = None if cache_path is None else str(cache_path).encode()
         self._check(self.lib.lbm_autotune(self.h, int(steps_per_candidate), cp, buf, 4096))

@@ -59,6 +59,7 @@ def test_invalid_arguments_rejected():
     J, g = C.c_double(), (C.c_double * 4)()
     assert lib.lbm_adjoint(None, C.byref(desc), C.byref(J), g) == -1
     assert lib.lbm_swimmer_set_params(None, 0, 1e-3, 1e-3, 1.0, 0.01) == -1
+    assert lib.lbm_autotune(None, 4, None, None, 0) == -1
     assert lib.lbm_strerror(-1) == b"invalid argument"
     assert lib.lbm_destroy(None) == 0
 

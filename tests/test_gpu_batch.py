@@ -119,6 +119,21 @@ def test_autotune_restores_state_and_caches(tmp_path):
     assert a.autotune(16, cache).startswith("cached")
 
 
+def test_tuner_is_disabled_and_changes_nothing():
+    # the tuner refuses to run (LBM_ESTATE) until the cause of the heap abort
+    # above is shown; the handle steps on unchanged
+    ens = wl.ensemble(seed=5, nboxes=2)
+    a = lbmib.batch_from_ensemble(ens)
+    b = lbmib.batch_from_ensemble(ens)
+    a.step(10)
+    b.step(10)
+    with pytest.raises(lbmib.LbmError, match="LBM_ESTATE"):
+        a.autotune(16)
+    a.step(5)
+    b.step(5)
+    assert np.array_equal(a.markers(), b.markers())
+
+
 def test_batch_with_an_empty_box_equals_single_boxes():
     # the middle box holds no swimmer (a gap in the bead -> box tables) and
     # runs Shan-Chen forcing; every box equals its own single-box run bit for bit
