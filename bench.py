@@ -198,15 +198,17 @@ def batch_section(lbmib, wl, steps=5000, warmup=200, seed=0):
             "launch": {"block": BATCH_LAUNCH[0], "xcd_remap": int(BATCH_LAUNCH[1]), "resident": BATCH_LAUNCH[2]}}
 
 
-def adjoint_section(lbmib, wl):
+def adjoint_section(lbmib, wl, use_graphs=True):
     """Gradient of a swimmer's displacement over one 2000-step period on the
     96^3 adjoint workload (checkpoints every 100 steps): wall time of
     lbm_adjoint (checkpointed forward + segment recompute + reverse sweep)
-    against the plain forward run of the same steps."""
+    against the plain forward run of the same steps.  use_graphs=False
+    launches every kernel directly (counter collection: the profiler's
+    counter mode does not survive replays of the two-stream graphs)."""
     case = wl.adjoint_case(reduced=False)
     T, K = case["steps"], case["checkpoint"]
     nodes = case["shape"][0] * case["shape"][1] * case["shape"][2]
-    lat = lbmib.from_workload(case)
+    lat = lbmib.from_workload(case, use_graphs=use_graphs)
     lat.step(200)
     lat.sync()
     t0 = time.perf_counter()
@@ -246,12 +248,15 @@ def paper_box_section(lbmib, wl, steps=500, warmup=50):
 
 def kernels_section(lbmib):
     """Full-grid stream-collide launches alone (serial launch mode, no
-    swimmer, uniform body force), FP32 and FP16-shifted storage, at 128^3
-    (populations of the order of the 256 MB last-level cache, which serves
-    part of the traffic) and at 256^3 (2.55 GB FP32, 1.27 GB FP16: HBM only):
-    mean launch duration from HIP events stamped by the dispatch packets,
-    algorithmic bytes (19 loads + 19 stores per node) per second against the
-    8 TB/s peak."""
+    swimmer), FP32 and FP16-shifted storage, at 128^3 (populations of the
+    order of the 256 MB last-level cache, which serves part of the traffic)
+    and at 256^3 (2.55 GB FP32, 1.27 GB FP16: HBM only): mean launch
+    duration from HIP events stamped by the dispatch packets, algorithmic
+    bytes (19 loads + 19 stores per node) per second against the 8 TB/s peak.
+    Each grid is timed twice on the same flow: with a uniform body force
+    (every node carries the Guo source term) and, keys ending in `_f0`, after
+    the force is switched off (as in the bulk of the swimmer workloads, where
+    the source term is skipped)."""
     out = {}
     for name, edge, storage in (("fp32_128", 128, lbmib.FP32_SHIFTED), ("fp16_128", 128, lbmib.FP16_SHIFTED),
                                 ("fp32_256", 256, lbmib.FP32_SHIFTED), ("fp16_256", 256, lbmib.FP16_SHIFTED)):
@@ -259,15 +264,19 @@ def kernels_section(lbmib):
         lat.set_body_force((1e-6, 0.0, 0.0))
         lat.set_stream_collide_launch(*KERNEL_LAUNCH)
         lat.step(20)
-        lat.set_kernel_timing(True)
-        lat.step(200)
-        kms, n = lat.kernel_time()
-        lat.set_kernel_timing(False)
-        lat.sync()
-        ms = kms / max(n, 1)
-        gbs = lat.bytes_per_step / (ms * 1e-3) / 1e9
-        out[name] = {"grid": [edge] * 3, "bytes_per_launch": lat.bytes_per_step, "avg_kernel_ms": round(ms, 5),
-                     "gbs": round(gbs, 1), "frac": round(gbs / PEAK_HBM_GBS, 4), "launches": n}
+        for key, force in ((name, (1e-6, 0.0, 0.0)), (name + "_f0", (0.0, 0.0, 0.0))):
+            lat.set_body_force(force)
+            lat.step(2)
+            lat.set_kernel_timing(True)
+            lat.step(200)
+            kms, n = lat.kernel_time()
+            lat.set_kernel_timing(False)
+            lat.sync()
+            ms = kms / max(n, 1)
+            gbs = lat.bytes_per_step / (ms * 1e-3) / 1e9
+            out[key] = {"grid": [edge] * 3, "bytes_per_launch": lat.bytes_per_step, "avg_kernel_ms": round(ms, 5),
+                        "gbs": round(gbs, 1), "frac": round(gbs / PEAK_HBM_GBS, 4), "launches": n,
+                        "body_force": force[0]}
         lat.close()
     return out
 
@@ -334,6 +343,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="run only the adjoint section (profiling of the reverse sweep)")
+    ap.add_argument("--direct", action="store_true",
+                    help="with --adjoint-only: launch kernels directly, no graph replays (counter runs)")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the full-grid stream-collide launches at 128^3 and 256^3 (counter runs)")
     ap.add_argument("--paper-length", type=int, default=0, metavar="PERIODS",
@@ -352,7 +363,10 @@ def main():
 
     torch.cuda.set_device(0)
     if args.adjoint_only:
-        print(json.dumps({"adjoint": adjoint_section(lbmib, wl)}), flush=True)
+        out = {"adjoint": adjoint_section(lbmib, wl, use_graphs=not args.direct)}
+        if args.direct:  # the copy probe calibrates the byte counters of the same run
+            out["copy_probe_gbs"] = lbmib.copy_bandwidth(1 << 30, 20)
+        print(json.dumps(out), flush=True)
         return
     if args.kernels_only:
         print(json.dumps({"kernels": kernels_section(lbmib), "copy_probe_gbs": lbmib.copy_bandwidth(1 << 30, 20)}),

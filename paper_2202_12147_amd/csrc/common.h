@@ -51,6 +51,9 @@ __host__ __device__ inline int near_slot(int64_t v) {
   return r < 0 ? r + kNearSlots : r;
 }
 constexpr int kPopBlock = 256; // nodes per population block (a power of two: shifts and masks)
+// mark_offset of launch_bead_stats that leaves the near blocks unmarked (the
+// near-block launch of the concurrent schedule marks them instead)
+constexpr int kNoMark = -(1 << 30);
 // Block counters of the persistent bulk launch: one per XCD (workgroups are
 // dealt to the 8 XCDs round robin) and step parity, each on its own 128-byte
 // line; Dev::work holds kWorkCounters ints.
@@ -70,6 +73,28 @@ enum Forcing { kGuo = 0, kShanChen = 1 };
 enum Storage { kFp32 = 0, kFp16 = 1, kFp32Plain = 2 };
 enum ScLaunch { kLaunchAll = 0, kLaunchBulk = 1, kLaunchActive = 2 };
 
+// Division of unsigned 32-bit numbers by an invariant d >= 1 through a
+// multiply-high and two shifts (Granlund and Montgomery, "Division by
+// invariant integers using multiplication", 1994, Fig. 4.1): with
+// l = ceil(log2 d) and m = floor(2^32 (2^l - d) / d) + 1,
+// n / d = (t + ((n - t) >> min(l, 1))) >> max(l - 1, 0), t = (m n) >> 32.
+struct Divisor {
+  uint32_t m;
+  int s1, s2;
+};
+
+__host__ __device__ inline Divisor make_divisor(uint32_t d) {
+  int l = 0;
+  while (((uint64_t)1 << l) < d) ++l;
+  const uint64_t m = (((uint64_t)1 << 32) * (((uint64_t)1 << l) - d)) / d + 1;
+  return Divisor{(uint32_t)m, l < 1 ? l : 1, l > 1 ? l - 1 : 0};
+}
+
+__host__ __device__ inline uint32_t divide(uint32_t n, const Divisor& v) {
+  const uint32_t t = (uint32_t)(((uint64_t)v.m * n) >> 32);
+  return (t + ((n - t) >> v.s1)) >> v.s2;
+}
+
 // One periodic box.  A single-box handle has exactly one.
 struct Box {
   int nx, ny, nz;
@@ -82,6 +107,7 @@ struct Box {
   int forcing;
   float tau, omega;     // tau and 1/tau
   float gx, gy, gz;     // uniform body force density
+  Divisor div_nx, div_ny;  // node id -> (x, y, z) without integer division
 };
 
 // Per-bead constant data.
@@ -169,17 +195,25 @@ struct Dev {
   int* near_list;
   int* near_count;
   int max_near, nsc, sc_bs;
+  // nonzero in the near-block launch of the concurrent schedule: nbeads extra
+  // workgroups mark the near blocks of the next step from the bead regions of
+  // this step (mark_near_blocks), off the bead-statistics kernel's path
+  int near_mark;
   // 1 when both population sets take at most kWriteThroughBytes: the
   // streaming stores are written through (stream_store) and the pulls are
   // non-temporal loads, which lets the last-level cache serve part of the
   // traffic; 0 above: non-temporal stores and plain (cached) pulls
   int small_pops;
+  // 1 when one population set takes less than 4 GiB: stream-collide
+  // addresses are 32-bit byte offsets from the set's start
+  int pops32;
   const int* tile_box;   // tile -> box (batches only)
   int* overflow;         // set when a bead region outgrows its reserved tiles
   int spread_blocks;
-  // per spread block (one per reserved tile of each bead), two int4:
-  // {bead, box, first bead of the box, beads in the box}, {kx, ky, kz, 0}
-  // the tile's offset within the bead's reserved tiles
+  // per spread block (two per reserved tile of each bead), two int4:
+  // {bead, box, first bead of the box, beads in the box}, {kx, ky, kz, half}:
+  // the tile's offset within the bead's reserved tiles and which four of its
+  // eight z layers the block fills
   const int4* spread_info;
   // (rho, u) of every node, written by the moment-recording stream-collide
   // variant only (segment recompute of the adjoint)
@@ -222,6 +256,8 @@ void launch_conserved(const Dev& d, int storage, int box, double* partial, int n
 // for that device (the address is looked up once and kept).
 constexpr int kNoAllocParts = 4096;
 hipError_t resolve_conserved_scratch(int device, double** out);
+// mark_offset: the near blocks of step (counter + sub + mark_offset) are
+// marked from the new bead regions; kNoMark: not marked.
 void launch_bead_stats(const Dev& d, int mark_offset, hipStream_t s);
 void launch_vertex_forces(const Dev& d, hipStream_t s);
 void launch_spread(const Dev& d, hipStream_t s);

@@ -31,6 +31,7 @@
 // small difference of O(1) numbers decides the result (metric change of a
 // triangle, dihedral angle change of a hinge, volume change).
 #include "common.h"
+#include "near_marks.h"
 
 namespace lbmib {
 
@@ -42,7 +43,6 @@ namespace {
 // the wave slots its retiring workgroups free).
 constexpr int kStatsBlock = 256;
 constexpr int kStatsBlockWide = 1024;
-constexpr int kTileNodes = kTile * kTile * kTile;  // 512
 constexpr int kSpreadBlock = 256;
 constexpr int kSpreadBlockWide = 512;
 constexpr int kWideBeads = 32;  // at most this many beads: wide workgroups
@@ -104,39 +104,6 @@ __device__ inline double block_sum(double v, double* sh) {
 // One workgroup per bead: centre (mean of nodes), bounding box and enclosed
 // volume, reduced in FP64 with wavefront shuffles, and from the box the node
 // region the bead's stencils can touch (in 8^3 tiles).
-// Mark the stream-collide blocks holding any node of [lo - 2, hi + 2] (per
-// axis, periodic) as near at step v, listing each newly marked block once.
-__device__ inline void mark_near_blocks(const Dev& d, const Box& B, int box, const int* lo, const int* hi,
-                                        int64_t v) {
-  const int p = (int)(v & 1), pf = near_slot(v);
-  const int first = d.nboxes == 1 ? 0 : d.sc_box_block0[box];
-  const int x0 = lo[0] - 2, nxs = hi[0] - lo[0] + 5;
-  const int ny_r = min(hi[1] - lo[1] + 5, B.ny), nz_r = min(hi[2] - lo[2] + 5, B.nz);
-  for (int r = threadIdx.x; r < ny_r * nz_r; r += blockDim.x) {
-    const int y = pmod(lo[1] - 2 + r % ny_r, B.ny), z = pmod(lo[2] - 2 + r / ny_r, B.nz);
-    const int row = (z * B.ny + y) * B.nx;  // box-local id of node (0, y, z)
-    int seg[2][2] = {{0, B.nx - 1}, {0, -1}};
-    if (nxs < B.nx) {
-      const int xs = pmod(x0, B.nx), xe = xs + nxs - 1;
-      seg[0][0] = xs;
-      seg[0][1] = min(xe, B.nx - 1);
-      if (xe >= B.nx) seg[1][1] = xe - B.nx;
-    }
-    for (int sgi = 0; sgi < 2; ++sgi) {
-      if (seg[sgi][1] < seg[sgi][0]) continue;
-      for (int blk = first + (row + seg[sgi][0]) / d.sc_bs; blk <= first + (row + seg[sgi][1]) / d.sc_bs; ++blk) {
-        if (atomicExch(&d.near[pf * d.nsc + blk], (int)v) != (int)v) {
-          const int i = atomicAdd(&d.near_count[p], 1);
-          if (i < d.max_near)
-            d.near_list[p * d.max_near + i] = blk;
-          else
-            atomicOr(d.overflow, 2);
-        }
-      }
-    }
-  }
-}
-
 template <int NW, int BS>
 __global__ __launch_bounds__(BS) void k_bead_stats(Dev d, int mark_offset) {
   constexpr int NWAVE = BS / 64;
@@ -280,7 +247,7 @@ __global__ __launch_bounds__(BS) void k_bead_stats(Dev d, int mark_offset) {
   }
   __syncthreads();
   // blocks the next step's stream-collide must treat as near this bead
-  mark_near_blocks(d, Bx, Bd.box, reg_lo, reg_hi, *d.step + d.sub + mark_offset);
+  if (mark_offset != kNoMark) mark_near_blocks(d, Bx, Bd.box, reg_lo, reg_hi, *d.step + d.sub + mark_offset);
 }
 
 // ---- membrane forces ------------------------------------------------------------
@@ -483,8 +450,10 @@ __device__ inline bool stencil_offset(int base, int origin, int extent, int N, i
   return false;
 }
 
-// One workgroup per tile.  The markers whose stencils meet the tile are
-// compacted in (bead, marker) order; the thread that finds a marker stages its
+// One workgroup per half tile (four of the tile's eight z layers: twice the
+// workgroups, each adding only the markers whose stencils meet its half).
+// The markers whose stencils meet the half tile are compacted in (bead,
+// marker) order; the thread that finds a marker stages its
 // stencil offset, its per-axis kernel weights and its force in LDS.  Entry e
 // goes to wavefront e % W (W wavefronts per workgroup), which adds the
 // marker's stencil (one lane per stencil node, all distinct) into the
@@ -524,10 +493,13 @@ __device__ inline bool covers(const SpreadBead& s, int tx, int ty, int tz, const
          pmod(tz - s.tlo[2], B.tz) < s.tcnt[2];
 }
 
+constexpr int kHalfLayers = kTile / 2;
+constexpr int kHalfNodes = kTile * kTile * kHalfLayers;  // 256
+
 template <int NW, int BS>
 __global__ __launch_bounds__(BS) void k_spread(Dev d) {
   constexpr int kSpreadWaves = BS / 64;
-  __shared__ float acc[kSpreadWaves][3][kTileNodes];
+  __shared__ float acc[kSpreadWaves][3][kHalfNodes];
   __shared__ SpreadEntry<NW> ent[BS];
   __shared__ int wave_cnt[kSpreadWaves];
   __shared__ SpreadBead sb[kSpreadBeads];
@@ -550,11 +522,14 @@ __global__ __launch_bounds__(BS) void k_spread(Dev d) {
   for (int i = 0; i < own; ++i)
     if (covers(spread_bead(d, sb, bead0, nb, i), tx, ty, tz, B)) return;  // an earlier bead owns this tile
   const int64_t n = *d.step + d.sub;
-  const int ox = tx * kTile, oy = ty * kTile, oz = tz * kTile;
-  const int ex = min(kTile, B.nx - ox), ey = min(kTile, B.ny - oy), ez = min(kTile, B.nz - oz);
+  // this workgroup's half: z layers [oz, oz + ez) of the tile, ez <= 4
+  const int ox = tx * kTile, oy = ty * kTile, oz = tz * kTile + kHalfLayers * kk.w;
+  const int ex = min(kTile, B.nx - ox), ey = min(kTile, B.ny - oy), ez = min(kHalfLayers, B.nz - oz);
+  if (kk.w == 0 && threadIdx.x == 0) d.stamp[B.tile0 + tx + B.tx * (ty + B.ty * tz)] = (int)n;
+  if (ez <= 0) return;  // the upper half of a short tile at the box's end holds no node
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
   for (int w = 0; w < kSpreadWaves; ++w)
-    for (int nd = threadIdx.x; nd < kTileNodes; nd += BS) {
+    for (int nd = threadIdx.x; nd < kHalfNodes; nd += BS) {
       acc[w][0][nd] = 0.0f;
       acc[w][1][nd] = 0.0f;
       acc[w][2][nd] = 0.0f;
@@ -644,7 +619,7 @@ __global__ __launch_bounds__(BS) void k_spread(Dev d) {
           const int lz = (E.off & 31) - 8 + sc;
           if ((unsigned)lx < (unsigned)ex && (unsigned)ly < (unsigned)ey && (unsigned)lz < (unsigned)ez) {
             const float w = E.w[0][sa] * E.w[1][sb_] * E.w[2][sc];
-            const int node = lx + kTile * (ly + kTile * lz);
+            const int node = lx + kTile * (ly + kTile * lz);  // lz < ez <= 4
             acc[wave][0][node] += w * E.f[0];
             acc[wave][1][node] += w * E.f[1];
             acc[wave][2][node] += w * E.f[2];
@@ -654,7 +629,7 @@ __global__ __launch_bounds__(BS) void k_spread(Dev d) {
     }
   }
   __syncthreads();
-  for (int nd = threadIdx.x; nd < kTileNodes; nd += BS) {
+  for (int nd = threadIdx.x; nd < kHalfNodes; nd += BS) {
     const int lx = nd % kTile, ly = (nd / kTile) % kTile, lz = nd / (kTile * kTile);
     if (lx < ex && ly < ey && lz < ez) {
       float ax = 0, ay = 0, az = 0;
@@ -669,7 +644,6 @@ __global__ __launch_bounds__(BS) void k_spread(Dev d) {
       d.F[2 * d.pstride + node] = az;
     }
   }
-  if (threadIdx.x == 0) d.stamp[B.tile0 + tx + B.tx * (ty + B.ty * tz)] = (int)n;
 }
 
 // ---- interpolation and advection -----------------------------------------------------

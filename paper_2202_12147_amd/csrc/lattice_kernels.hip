@@ -19,6 +19,7 @@
 #include <hip/hip_fp16.h>
 
 #include "common.h"
+#include "near_marks.h"
 
 #include <hip/hip_ext.h>
 
@@ -95,7 +96,7 @@ __device__ inline Nbr neighbours(int x, int y, int z, int nx, int ny, int nz) {
 // NTLD: non-temporal loads (populations of the last-level-cache size) or
 // plain ones (larger sets: 2 % faster on 10 GB of populations, 8 % slower at
 // 128^3).
-template <int ST, bool NTLD = true>
+template <int ST, bool NTLD = true, bool OFF32 = false>
 __device__ inline void pull(const typename PopIO<ST>::T* __restrict__ src, int64_t base, const Nbr& o, float inv,
                             float* g) {
   using IO = PopIO<ST>;
@@ -104,10 +105,32 @@ __device__ inline void pull(const typename PopIO<ST>::T* __restrict__ src, int64
                        o.xm + o.ym, o.xp + o.yp, o.xm + o.yp, o.xp + o.ym,
                        o.xm + o.zm, o.xp + o.zp, o.xm + o.zp, o.xp + o.zm,
                        o.ym + o.zm, o.yp + o.zp, o.ym + o.zp, o.yp + o.zm};
-  // addresses relative to the node's own population block: 32-bit lane and
-  // population offsets, one 64-bit multiply-add per population for the block
-  const typename PopIO<ST>::T* bp = src + (base / kPopBlock) * (int64_t)(kQ * kPopBlock);
   const int lane = (int)(base % kPopBlock);
+  if constexpr (OFF32) {
+    // A population set below 4 GiB: 32-bit byte offsets from the set's start,
+    // which is uniform over the launch, so each load takes one offset
+    // register and no 64-bit address arithmetic.  The neighbour's element is
+    // the node's own plus q * 256 + off + 4608 db (db = its block step:
+    // 19 * 256 - 256 elements per block beyond the 256 the offset covers).
+    using T = typename PopIO<ST>::T;
+    const char* s8 = reinterpret_cast<const char*>(src);
+    const uint32_t e0 = (uint32_t)(base / kPopBlock) * (uint32_t)(kQ * kPopBlock) + (uint32_t)lane;
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+      const int db = (lane + off[q]) >> 8;  // floor((lane + off) / kPopBlock)
+      const uint32_t e = e0 + (uint32_t)(off[q] + db * (kQ * kPopBlock - kPopBlock));
+      const T* a = reinterpret_cast<const T*>(s8 + e * (uint32_t)sizeof(T)) + q * kPopBlock;
+      if constexpr (NTLD)
+        g[q] = IO::ld(a, q, inv);
+      else
+        g[q] = IO::ld_cached(a, q, inv);
+    }
+    return;
+  } else {
+  // larger sets: addresses relative to the node's own population block,
+  // 32-bit lane and population offsets, one 64-bit multiply-add per
+  // population for the block
+  const typename PopIO<ST>::T* bp = src + (base / kPopBlock) * (int64_t)(kQ * kPopBlock);
 #pragma unroll
   for (int q = 0; q < kQ; ++q) {
     const int rel = lane + off[q];
@@ -117,6 +140,7 @@ __device__ inline void pull(const typename PopIO<ST>::T* __restrict__ src, int64
       g[q] = IO::ld(a, q, inv);
     else
       g[q] = IO::ld_cached(a, q, inv);
+  }
   }
 }
 
@@ -144,19 +168,59 @@ __device__ inline Moments moments(const float* g) {
 // compiler, which product is fused can differ between template instances of
 // the caller and change the last bit, and the launch variants of the step
 // must agree bit for bit.
+// 1/rho from the hardware reciprocal (within one ulp; rho stays near 1 in
+// these flows), in place of the correctly rounded division sequence
+__device__ inline float inv_density(float rho) { return __builtin_amdgcn_rcpf(rho); }
+
+// SRC = false: the source term is zero (no force at the node, or Shan-Chen
+// forcing) and is left out of the arithmetic; the populations are the same
+// as with the zero term added (up to the sign of an exact zero).
+template <bool SRC>
 __device__ inline void collide_pair(float& gp, float& gm, float w, float om, float drho, float rho,
                                     float usq15, float e, float src_a, float cu, float cf,
                                     float uf) {
   const float sym = w * (drho + rho * fmaf(4.5f * e, e, -usq15));
   const float wr3 = w * rho * 3.0f;
   const float eqp = fmaf(wr3, e, sym), eqm = fmaf(-wr3, e, sym);
-  // Guo source: src_a (1 - om/2) w [3 (c - u).F + 9 (c.u)(c.F)], zero for Shan-Chen
-  const float sw = src_a * w;
-  const float s_sym = sw * fmaf(9.0f * cu, cf, -3.0f * uf);
-  const float sw3 = sw * 3.0f;
-  const float sp = fmaf(sw3, cf, s_sym), sm = fmaf(-sw3, cf, s_sym);
-  gp = gp + om * (eqp - gp) + sp;
-  gm = gm + om * (eqm - gm) + sm;
+  if constexpr (SRC) {
+    // Guo source: src_a (1 - om/2) w [3 (c - u).F + 9 (c.u)(c.F)]
+    const float sw = src_a * w;
+    const float s_sym = sw * fmaf(9.0f * cu, cf, -3.0f * uf);
+    const float sw3 = sw * 3.0f;
+    const float sp = fmaf(sw3, cf, s_sym), sm = fmaf(-sw3, cf, s_sym);
+    gp = gp + om * (eqp - gp) + sp;
+    gm = gm + om * (eqm - gm) + sm;
+  } else {
+    gp = gp + om * (eqp - gp);
+    gm = gm + om * (eqm - gm);
+  }
+}
+
+// BGK collision of all 19 populations (with the Guo source when SRC).
+template <bool SRC>
+__device__ inline void collide_all(float* g, const Moments& m, float om, float ex, float ey, float ez, float src_a,
+                                   float ux, float uy, float uz, float Fx, float Fy, float Fz) {
+  const float usq15 = 1.5f * fmaf(ez, ez, fmaf(ey, ey, ex * ex));
+  const float uf = SRC ? fmaf(uz, Fz, fmaf(uy, Fy, ux * Fx)) : 0.0f;
+  // rest population
+  {
+    const float eq0 = kW0 * (m.drho - m.rho * usq15);
+    if constexpr (SRC)
+      g[0] = g[0] + om * (eq0 - g[0]) + src_a * kW0 * (-3.0f * uf);
+    else
+      g[0] = g[0] + om * (eq0 - g[0]);
+  }
+  // faces
+  collide_pair<SRC>(g[1], g[2], kW1, om, m.drho, m.rho, usq15, ex, src_a, ux, Fx, uf);
+  collide_pair<SRC>(g[3], g[4], kW1, om, m.drho, m.rho, usq15, ey, src_a, uy, Fy, uf);
+  collide_pair<SRC>(g[5], g[6], kW1, om, m.drho, m.rho, usq15, ez, src_a, uz, Fz, uf);
+  // edges
+  collide_pair<SRC>(g[7], g[8], kW2, om, m.drho, m.rho, usq15, ex + ey, src_a, ux + uy, Fx + Fy, uf);
+  collide_pair<SRC>(g[9], g[10], kW2, om, m.drho, m.rho, usq15, ex - ey, src_a, ux - uy, Fx - Fy, uf);
+  collide_pair<SRC>(g[11], g[12], kW2, om, m.drho, m.rho, usq15, ex + ez, src_a, ux + uz, Fx + Fz, uf);
+  collide_pair<SRC>(g[13], g[14], kW2, om, m.drho, m.rho, usq15, ex - ez, src_a, ux - uz, Fx - Fz, uf);
+  collide_pair<SRC>(g[15], g[16], kW2, om, m.drho, m.rho, usq15, ey + ez, src_a, uy + uz, Fy + Fz, uf);
+  collide_pair<SRC>(g[17], g[18], kW2, om, m.drho, m.rho, usq15, ey - ez, src_a, uy - uz, Fy - Fz, uf);
 }
 
 // Workgroup -> logical block.  Workgroups are handed to the 8 XCDs round
@@ -173,7 +237,7 @@ __device__ inline int logical_block(int remap, int nblocks) {
 // `forced`: read F and write u at this node (its tile is active this step).
 // `avg`: add u to the node's time-average sums (a sampled step).
 // MOM: also record (rho, u) of the node in d.mom.
-template <int ST, bool MOM = false, bool NTLD = true>
+template <int ST, bool MOM = false, bool NTLD = true, bool OFF32 = false>
 __device__ inline void sc_node(const Dev& d, const Box& B, int x, int y, int z, int64_t base,
                                int64_t n, bool forced, bool avg) {
   using IO = PopIO<ST>;
@@ -191,7 +255,7 @@ __device__ inline void sc_node(const Dev& d, const Box& B, int x, int y, int z, 
     a2 = d.uavg[2 * ps + base];
   }
   float g[kQ];
-  pull<ST, NTLD>(src, base, o, d.fp16_inv, g);
+  pull<ST, NTLD, OFF32>(src, base, o, d.fp16_inv, g);
   const Moments m = moments(g);
 
   float Fx = B.gx, Fy = B.gy, Fz = B.gz;
@@ -200,7 +264,7 @@ __device__ inline void sc_node(const Dev& d, const Box& B, int x, int y, int z, 
     Fy += d.F[ps + base];
     Fz += d.F[2 * ps + base];
   }
-  const float ir = 1.0f / m.rho;
+  const float ir = inv_density(m.rho);
   const float ux = (m.jx + 0.5f * Fx) * ir;
   const float uy = (m.jy + 0.5f * Fy) * ir;
   const float uz = (m.jz + 0.5f * Fz) * ir;
@@ -220,32 +284,33 @@ __device__ inline void sc_node(const Dev& d, const Box& B, int x, int y, int z, 
     ez = (m.jz + B.tau * Fz) * ir;
     src_a = 0.0f;
   }
-  const float om = B.omega;
-  const float usq15 = 1.5f * fmaf(ez, ez, fmaf(ey, ey, ex * ex));
-  const float uf = fmaf(uz, Fz, fmaf(uy, Fy, ux * Fx));
-  // rest population
-  {
-    const float eq0 = kW0 * (m.drho - m.rho * usq15);
-    g[0] = g[0] + om * (eq0 - g[0]) + src_a * kW0 * (-3.0f * uf);
-  }
-  // faces
-  collide_pair(g[1], g[2], kW1, om, m.drho, m.rho, usq15, ex, src_a, ux, Fx, uf);
-  collide_pair(g[3], g[4], kW1, om, m.drho, m.rho, usq15, ey, src_a, uy, Fy, uf);
-  collide_pair(g[5], g[6], kW1, om, m.drho, m.rho, usq15, ez, src_a, uz, Fz, uf);
-  // edges
-  collide_pair(g[7], g[8], kW2, om, m.drho, m.rho, usq15, ex + ey, src_a, ux + uy, Fx + Fy, uf);
-  collide_pair(g[9], g[10], kW2, om, m.drho, m.rho, usq15, ex - ey, src_a, ux - uy, Fx - Fy, uf);
-  collide_pair(g[11], g[12], kW2, om, m.drho, m.rho, usq15, ex + ez, src_a, ux + uz, Fx + Fz, uf);
-  collide_pair(g[13], g[14], kW2, om, m.drho, m.rho, usq15, ex - ez, src_a, ux - uz, Fx - Fz, uf);
-  collide_pair(g[15], g[16], kW2, om, m.drho, m.rho, usq15, ey + ez, src_a, uy + uz, Fy + Fz, uf);
-  collide_pair(g[17], g[18], kW2, om, m.drho, m.rho, usq15, ey - ez, src_a, uy - uz, Fy - Fz, uf);
-  T* const bq = dst + (base / kPopBlock) * (int64_t)(kQ * kPopBlock) + (int)(base % kPopBlock);
-  if (d.small_pops) {
+  // no force at the node (most nodes) or Shan-Chen forcing: no source term
+  if (src_a != 0.0f && (Fx != 0.0f || Fy != 0.0f || Fz != 0.0f))
+    collide_all<true>(g, m, B.omega, ex, ey, ez, src_a, ux, uy, uz, Fx, Fy, Fz);
+  else
+    collide_all<false>(g, m, B.omega, ex, ey, ez, src_a, ux, uy, uz, Fx, Fy, Fz);
+  if constexpr (OFF32) {
+    // 32-bit byte offsets from the set's start (see pull)
+    // one offset register for all 19 stores: the population's q * 256
+    // elements are a constant the store instruction carries
+    const uint32_t e0 = (uint32_t)(base / kPopBlock) * (uint32_t)(kQ * kPopBlock) + (uint32_t)(base % kPopBlock);
+    T* const bq = reinterpret_cast<T*>(reinterpret_cast<char*>(dst) + e0 * (uint32_t)sizeof(T));
+    if (d.small_pops) {
 #pragma unroll
-    for (int q = 0; q < kQ; ++q) IO::st_wt(bq + q * kPopBlock, q, g[q], d.fp16_scale);
+      for (int q = 0; q < kQ; ++q) IO::st_wt(bq + q * kPopBlock, q, g[q], d.fp16_scale);
+    } else {
+#pragma unroll
+      for (int q = 0; q < kQ; ++q) IO::st(bq + q * kPopBlock, q, g[q], d.fp16_scale);
+    }
   } else {
+    T* const bq = dst + (base / kPopBlock) * (int64_t)(kQ * kPopBlock) + (int)(base % kPopBlock);
+    if (d.small_pops) {
 #pragma unroll
-    for (int q = 0; q < kQ; ++q) IO::st(bq + q * kPopBlock, q, g[q], d.fp16_scale);
+      for (int q = 0; q < kQ; ++q) IO::st_wt(bq + q * kPopBlock, q, g[q], d.fp16_scale);
+    } else {
+#pragma unroll
+      for (int q = 0; q < kQ; ++q) IO::st(bq + q * kPopBlock, q, g[q], d.fp16_scale);
+    }
   }
   if (avg) {
     double* __restrict__ acc = d.uavg;
@@ -278,10 +343,10 @@ __device__ inline void sc_block(const Dev& d, int blk, int64_t n, bool bulk, boo
   const int first = d.nboxes == 1 ? 0 : d.sc_box_block0[b];
   const int id = (blk - first) * BS + (int)threadIdx.x;
   if (id >= B.n) return;
-  const int x = id % B.nx;
-  const int yz = id / B.nx;
-  const int y = yz % B.ny;
-  const int z = yz / B.ny;
+  const int yz = (int)divide((uint32_t)id, B.div_nx);
+  const int x = id - yz * B.nx;
+  const int z = (int)divide((uint32_t)yz, B.div_ny);
+  const int y = yz - z * B.ny;
   // nodes of the bulk launch are never forced: every node a stencil reaches
   // lies in a near block, and an active tile's other nodes carry F = 0
   bool forced = false;
@@ -289,7 +354,12 @@ __device__ inline void sc_block(const Dev& d, int blk, int64_t n, bool bulk, boo
     const int tile = B.tile0 + (x / kTile) + B.tx * ((y / kTile) + B.ty * (z / kTile));
     forced = d.stamp[tile] == (int)n;
   }
-  sc_node<ST, MOM, NTLD>(d, B, x, y, z, B.node0 + id, n, forced, avg);
+  // the two addressing forms as separate code (a population set below 4 GiB
+  // takes 32-bit offsets)
+  if (d.pops32)
+    sc_node<ST, MOM, NTLD, true>(d, B, x, y, z, B.node0 + id, n, forced, avg);
+  else
+    sc_node<ST, MOM, NTLD, false>(d, B, x, y, z, B.node0 + id, n, forced, avg);
 }
 
 // AVG: the variant launched while a time average of u runs (the sampling
@@ -301,6 +371,21 @@ __global__ __launch_bounds__(BS) void k_stream_collide(Dev d, int remap, int nbl
   const int pp = (int)(pn & 1), pf = near_slot(pn);
   const bool avg = AVG && avg_sampled(d, n);
   if constexpr (MODE == kScActive) {
+    if ((int)blockIdx.x >= d.max_near) {
+      // the near blocks of step n + 1 around bead blockIdx.x - max_near, from
+      // the bead region its statistics kernel found at step n
+      const int b = (int)blockIdx.x - d.max_near;
+      const BeadState& st = d.bstate[b];
+      const int box = d.beads[b].box;
+      __shared__ int reg[6];
+      if (threadIdx.x < 3) {
+        reg[threadIdx.x] = st.lo[threadIdx.x];
+        reg[3 + threadIdx.x] = st.hi[threadIdx.x];
+      }
+      __syncthreads();
+      mark_near_blocks(d, d.boxes[box], box, reg, reg + 3, n);
+      return;
+    }
     const int cnt = min(d.near_count[pp], d.max_near);
     if ((int)blockIdx.x < cnt)
       sc_block<ST, BS, false, NTLD>(d, d.near_list[pp * d.max_near + blockIdx.x], n, false, avg);
@@ -436,7 +521,7 @@ __global__ __launch_bounds__(kScBlock) void k_velocity(Dev d, float* __restrict_
     Fy += d.F[ps + base];
     Fz += d.F[2 * ps + base];
   }
-  const float ir = 1.0f / m.rho;
+  const float ir = inv_density(m.rho);
   if (uo) {
     uo[ob] = (m.jx + 0.5f * Fx) * ir;
     uo[nb + ob] = (m.jy + 0.5f * Fy) * ir;
@@ -557,7 +642,7 @@ template <int ST, int MODE, bool AVG, bool NTLD>
 static void launch_sc_mode(const Dev& d, int block, int nblocks, int remap, int resident, int ncu,
                            hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   int grid = remap ? (nblocks + 7) / 8 * 8 : nblocks;
-  if (MODE == kScActive) grid = d.max_near;
+  if (MODE == kScActive) grid = d.max_near + (d.near_mark ? d.nbeads : 0);
   if (MODE == kScBulk && resident > 0)
     grid = remap ? std::min(grid, ncu * resident) / 8 * 8 : std::min(grid, ncu * resident);
   if (MODE != kScBulk) resident = 0;

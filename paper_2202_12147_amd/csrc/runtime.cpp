@@ -253,8 +253,9 @@ int upload(lbm_handle* h) {
     if (B.nbeads == 0) B.bead0 = (int)b;
     B.nbeads += 1;
   }
-  // spread candidate blocks, one per reserved tile of each bead: {bead, box,
-  // first bead of the box, beads of the box}, {tile offsets kx, ky, kz}
+  // spread candidate blocks, two per reserved tile of each bead (the lower
+  // and upper four z layers): {bead, box, first bead of the box, beads of the
+  // box}, {tile offsets kx, ky, kz, half}
   std::vector<int> spread_info;
   for (size_t b = 0; b < h->beads.size(); ++b) {
     Bead& Bd = h->beads[b];
@@ -262,10 +263,11 @@ int upload(lbm_handle* h) {
     Bd.tile_block0 = (int)(spread_info.size() / 8);
     for (int kz = 0; kz < Bd.tiles_z; ++kz)
       for (int ky = 0; ky < Bd.tiles_y; ++ky)
-        for (int kx = 0; kx < Bd.tiles_x; ++kx) {
-          const int e[8] = {(int)b, Bd.box, B.bead0, B.nbeads, kx, ky, kz, 0};
-          spread_info.insert(spread_info.end(), e, e + 8);
-        }
+        for (int kx = 0; kx < Bd.tiles_x; ++kx)
+          for (int half = 0; half < 2; ++half) {
+            const int e[8] = {(int)b, Bd.box, B.bead0, B.nbeads, kx, ky, kz, half};
+            spread_info.insert(spread_info.end(), e, e + 8);
+          }
   }
   h->spread_blocks = (int)(spread_info.size() / 8);
 
@@ -453,7 +455,7 @@ void enqueue_steps(lbm_handle* h, int64_t count) {
     hipEvent_t ev_bulk = h->step_events[2 * (i % kGraphChunk)], ev_near = h->step_events[2 * (i % kGraphChunk) + 1];
     d.sub = (int)i;
     if (i > 0) launch_interp_advance(d, h->side);
-    launch_bead_stats(d, 0, h->side);
+    launch_bead_stats(d, kNoMark, h->side);  // the near-block launch marks the next step's blocks
     launch_vertex_forces(d, h->side);
     launch_spread(d, h->side);
     if (prev_near) (void)hipStreamWaitEvent(h->stream, prev_near, 0);
@@ -464,7 +466,9 @@ void enqueue_steps(lbm_handle* h, int64_t count) {
     (void)hipEventRecord(ev_bulk, h->stream);
     if (prev_bulk) (void)hipStreamWaitEvent(h->side, prev_bulk, 0);
     timing_pair(h, &e0, &e1);
-    launch_stream_collide(d, h->storage, kLaunchActive, h->sc_block, h->sc_blocks, 0, 0, h->ncu, h->side, e0, e1);
+    Dev dn = d;
+    dn.near_mark = 1;
+    launch_stream_collide(dn, h->storage, kLaunchActive, h->sc_block, h->sc_blocks, 0, 0, h->ncu, h->side, e0, e1);
     (void)hipEventRecord(ev_near, h->side);
     prev_bulk = ev_bulk;
     prev_near = ev_near;
@@ -638,6 +642,8 @@ int create_boxes(const lbm_box_desc* boxes, int nboxes, const lbm_opts* opts, lb
     B.forcing = d.forcing;
     B.tau = (float)d.tau;
     B.omega = (float)(1.0 / d.tau);
+    B.div_nx = make_divisor((uint32_t)B.nx);
+    B.div_ny = make_divisor((uint32_t)B.ny);
     const int nb = (int)((B.n + kScBlock - 1) / kScBlock);
     block_box.insert(block_box.end(), nb, b);
     node0 += B.n;
@@ -730,6 +736,7 @@ int create_boxes(const lbm_box_desc* boxes, int nboxes, const lbm_opts* opts, lb
   d.sub = 0;
   d.fp16_scale = h->fp16_scale;
   d.small_pops = 2 * kQ * h->pstride * (int64_t)element_bytes(h) <= kWriteThroughBytes ? 1 : 0;
+  d.pops32 = kQ * h->pstride * (int64_t)element_bytes(h) < ((int64_t)1 << 32) ? 1 : 0;
   d.fp16_inv = 1.0f / h->fp16_scale;
   d.width = h->width;
   d.overflow = h->d_overflow;

@@ -11,6 +11,7 @@ errors average out: velocity rel-L2 measured 1.1e-4 (bar 5e-4), swimmer
 displacement within 1.4e-3 relative (bar 3e-3).  Unscaled storage (S = 1)
 leaves every deviation subnormal (step 6e-8) and is shown to fail."""
 import math
+import os
 
 import numpy as np
 import pytest
@@ -23,6 +24,7 @@ from tests.helpers import max_rel, oracle_from, rel_l2
 pytestmark = pytest.mark.gpu
 
 S27 = 2.0 ** 27
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 
 def test_scale_rule():
@@ -136,3 +138,40 @@ def test_fp16_above_the_write_through_size():
     dr = np.abs(lat.markers() - o.markers()).max()
     print("fp16 256^3: u rel-L2", du, "max-rel", dmax, "max |dr|", dr, flush=True)
     assert du < 3e-4 and dmax < 4e-4 and dr < 1e-6
+
+
+@pytest.mark.parametrize("arrangement", ["collinear", "side"])
+def test_pair_full_length_vs_stored_oracle(arrangement):
+    """The two-swimmer 256x128x128 workload over its full 10000 steps in the
+    benchmark's launch shapes, FP32- and FP16-shifted storage, against the
+    FP64 oracle's run stored by tests/golden/make_trajectory_golden.py: both
+    swimmer centres every 10 steps, every marker and the final velocity field
+    on every fourth node per axis.  Reported: the largest centre error
+    relative to the largest centre displacement, the final field's rel-L2 and
+    element-wise error on the sampled nodes, the largest marker error."""
+    ref = np.load(os.path.join(GOLDEN, f"pair256_{arrangement}_10000.npz"))
+    Xr, every = ref["X"], int(ref["every"])
+    case = wl.pair_256(seed=0, arrangement=arrangement)
+    disp = np.abs(Xr - Xr[0]).max()
+    res = {}
+    for name, st, S, launch in (("fp32", lbmib.FP32_SHIFTED, 1.0, bench.MAIN_LAUNCH),
+                                ("fp16", lbmib.FP16_SHIFTED, S27, bench.FP16_LAUNCH)):
+        lat = lbmib.from_workload(case, storage=st, fp16_scale=S)
+        lat.set_stream_collide_launch(*launch)
+        np.testing.assert_allclose(lat.swimmer_centres(), Xr[0], rtol=0, atol=1e-12)
+        worst = 0.0
+        for k in range(1, len(Xr)):
+            lat.step(every)
+            worst = max(worst, float(np.abs(lat.swimmer_centres() - Xr[k]).max()))
+        u = lat.velocity()[:, ::4, ::4, ::4]
+        res[name] = dict(centre=worst / disp, u_l2=rel_l2(u, ref["u_sub"]), u_max=max_rel(u, ref["u_sub"]),
+                         markers=float(np.abs(lat.markers() - ref["markers"]).max()))
+        lat.close()
+    print(arrangement, f"largest displacement {disp:.4e}:", res, flush=True)
+    # measured (collinear): FP32 centre 1.4e-4, field rel-L2 3.2e-6 and
+    # element-wise 8.8e-7, markers 9.5e-8; FP16 centre 1.1e-3, field 2.5e-4
+    # and 2.1e-4, markers 9.4e-7.  Bars about three times those.
+    assert res["fp32"]["centre"] < 5e-4 and res["fp32"]["u_l2"] < 1e-5 and res["fp32"]["u_max"] < 5e-6
+    assert res["fp32"]["markers"] < 5e-7
+    assert res["fp16"]["centre"] < 4e-3 and res["fp16"]["u_l2"] < 1e-3 and res["fp16"]["u_max"] < 1e-3
+    assert res["fp16"]["markers"] < 5e-6
