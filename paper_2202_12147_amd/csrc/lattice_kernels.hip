@@ -32,6 +32,10 @@ namespace {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
+// Fourth word of a raw buffer resource on this architecture (32-bit data
+// format; stride 0, so the range check is against the byte count)
+constexpr int kBufferWord3 = 0x00020000;
+
 constexpr float kW0 = 1.0f / 3.0f;
 constexpr float kW1 = 1.0f / 18.0f;
 constexpr float kW2 = 1.0f / 36.0f;
@@ -45,6 +49,9 @@ __device__ constexpr float weight(int q) { return q == 0 ? kW0 : (q < 7 ? kW1 : 
 template <>
 struct PopIO<kFp32> {
   using T = float;
+  using Raw = unsigned;
+  static constexpr int kNtAux = 2;  // non-temporal buffer loads (the nt bit)
+  __device__ static inline float decode(Raw r, int, float) { return __uint_as_float(r); }
   __device__ static inline float ld(const float* p, int, float) { return __builtin_nontemporal_load(p); }
   __device__ static inline float ld_cached(const float* p, int, float) { return *p; }
   __device__ static inline void st(float* p, int, float v, float) { __builtin_nontemporal_store(v, p); }
@@ -54,6 +61,9 @@ struct PopIO<kFp32> {
 template <>
 struct PopIO<kFp16> {
   using T = __half;
+  using Raw = unsigned short;
+  static constexpr int kNtAux = 0;  // half loads stay plain (measured faster)
+  __device__ static inline float decode(Raw r, int, float inv) { return __half2float(__ushort_as_half(r)) * inv; }
   __device__ static inline float ld(const __half* p, int, float inv) { return __half2float(*p) * inv; }
   __device__ static inline float ld_cached(const __half* p, int q, float inv) { return ld(p, q, inv); }
   __device__ static inline void st(__half* p, int, float v, float scale) { *p = __float2half_rn(v * scale); }
@@ -67,6 +77,9 @@ struct PopIO<kFp16> {
 template <>
 struct PopIO<kFp32Plain> {
   using T = float;
+  using Raw = unsigned;
+  static constexpr int kNtAux = 2;
+  __device__ static inline float decode(Raw r, int q, float) { return __uint_as_float(r) - weight(q); }
   __device__ static inline float ld(const float* p, int q, float) {
     return __builtin_nontemporal_load(p) - weight(q);
   }
@@ -98,7 +111,7 @@ __device__ inline Nbr neighbours(int x, int y, int z, int nx, int ny, int nz) {
 // 128^3).
 template <int ST, bool NTLD = true, bool OFF32 = false>
 __device__ inline void pull(const typename PopIO<ST>::T* __restrict__ src, int64_t base, const Nbr& o, float inv,
-                            float* g) {
+                            float* g, uint32_t set_bytes = 0) {
   using IO = PopIO<ST>;
   const int off[kQ] = {0,
                        o.xm, o.xp, o.ym, o.yp, o.zm, o.zp,
@@ -107,23 +120,35 @@ __device__ inline void pull(const typename PopIO<ST>::T* __restrict__ src, int64
                        o.ym + o.zm, o.yp + o.zp, o.ym + o.zp, o.yp + o.zm};
   const int lane = (int)(base % kPopBlock);
   if constexpr (OFF32) {
-    // A population set below 4 GiB: 32-bit byte offsets from the set's start,
-    // which is uniform over the launch, so each load takes one offset
-    // register and no 64-bit address arithmetic.  The neighbour's element is
-    // the node's own plus q * 256 + off + 4608 db (db = its block step:
-    // 19 * 256 - 256 elements per block beyond the 256 the offset covers).
+    // A population set below 4 GiB (set_bytes): buffer loads with a 32-bit
+    // byte offset per node and the population's constant offset split into a
+    // scalar part (multiples of 4 KiB) and the instruction's immediate field,
+    // so each load takes one offset register and no 64-bit address
+    // arithmetic.  Node m sits at element (m / 256) * 19 * 256 + m % 256 =
+    // m + 4608 (m >> 8) of population 0; in bytes, with M = m * sizeof(T):
+    // M + 4608 sizeof(T) (M >> (8 + log2 sizeof(T))).  Per population: one
+    // add (the neighbour's M), one shift, one 24-bit multiply-add
+    // (m >> 8 < 2^23).
     using T = typename PopIO<ST>::T;
-    const char* s8 = reinterpret_cast<const char*>(src);
-    const uint32_t e0 = (uint32_t)(base / kPopBlock) * (uint32_t)(kQ * kPopBlock) + (uint32_t)lane;
+    using Raw = typename IO::Raw;
+    constexpr uint32_t kSz = (uint32_t)sizeof(T);
+    constexpr int kSh = 8 + (kSz == 4 ? 2 : kSz == 2 ? 1 : 0);
+    constexpr uint32_t kBlockStep = (kQ - 1) * kPopBlock * kSz;
+    constexpr int kAux = NTLD ? IO::kNtAux : 0;
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(src), (short)0, (int)set_bytes, kBufferWord3);
+    const uint32_t M = (uint32_t)base * kSz;
 #pragma unroll
     for (int q = 0; q < kQ; ++q) {
-      const int db = (lane + off[q]) >> 8;  // floor((lane + off) / kPopBlock)
-      const uint32_t e = e0 + (uint32_t)(off[q] + db * (kQ * kPopBlock - kPopBlock));
-      const T* a = reinterpret_cast<const T*>(s8 + e * (uint32_t)sizeof(T)) + q * kPopBlock;
-      if constexpr (NTLD)
-        g[q] = IO::ld(a, q, inv);
+      const uint32_t Mn = M + (uint32_t)off[q] * kSz;  // the neighbour's node, in bytes (wraps to in-box)
+      const uint32_t b = __umul24(Mn >> kSh, kBlockStep) + Mn;
+      const uint32_t c = (uint32_t)q * kPopBlock * kSz;  // population q's block offset
+      Raw r;
+      if constexpr (kSz == 2)
+        r = __builtin_amdgcn_raw_buffer_load_b16(rs, b + (c & 4095u), c & ~4095u, kAux);
       else
-        g[q] = IO::ld_cached(a, q, inv);
+        r = __builtin_amdgcn_raw_buffer_load_b32(rs, b + (c & 4095u), c & ~4095u, kAux);
+      g[q] = IO::decode(r, q, inv);
     }
     return;
   } else {
@@ -255,7 +280,7 @@ __device__ inline void sc_node(const Dev& d, const Box& B, int x, int y, int z, 
     a2 = d.uavg[2 * ps + base];
   }
   float g[kQ];
-  pull<ST, NTLD, OFF32>(src, base, o, d.fp16_inv, g);
+  pull<ST, NTLD, OFF32>(src, base, o, d.fp16_inv, g, (uint32_t)(kQ * d.pstride * (int64_t)sizeof(T)));
   const Moments m = moments(g);
 
   float Fx = B.gx, Fy = B.gy, Fz = B.gz;
@@ -293,8 +318,10 @@ __device__ inline void sc_node(const Dev& d, const Box& B, int x, int y, int z, 
     // 32-bit byte offsets from the set's start (see pull)
     // one offset register for all 19 stores: the population's q * 256
     // elements are a constant the store instruction carries
-    const uint32_t e0 = (uint32_t)(base / kPopBlock) * (uint32_t)(kQ * kPopBlock) + (uint32_t)(base % kPopBlock);
-    T* const bq = reinterpret_cast<T*>(reinterpret_cast<char*>(dst) + e0 * (uint32_t)sizeof(T));
+    constexpr uint32_t kSz = (uint32_t)sizeof(T);
+    constexpr int kSh = 8 + (kSz == 4 ? 2 : kSz == 2 ? 1 : 0);
+    const uint32_t M = (uint32_t)base * kSz;
+    T* const bq = reinterpret_cast<T*>(reinterpret_cast<char*>(dst) + (__umul24(M >> kSh, (kQ - 1) * kPopBlock * kSz) + M));
     if (d.small_pops) {
 #pragma unroll
       for (int q = 0; q < kQ; ++q) IO::st_wt(bq + q * kPopBlock, q, g[q], d.fp16_scale);
