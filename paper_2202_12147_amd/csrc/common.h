@@ -21,6 +21,7 @@ namespace lbmib {
 
 constexpr int kQ = 19;
 constexpr int kTile = 8;       // active-tile edge in nodes
+constexpr int kSpreadParts = 4;  // spreading workgroups per tile, each kTile / kSpreadParts z layers
 constexpr int kScBlock = 256;  // stream-collide threads per block
 // Near-block flags hold three step slots (step mod 3): the bead statistics of
 // step n mark slot n mod 3 while the bulk launch of step n - 1, which may
@@ -211,9 +212,9 @@ struct Dev {
   int* overflow;         // set when a bead region outgrows its reserved tiles
   int spread_blocks;
   // per spread block (two per reserved tile of each bead), two int4:
-  // {bead, box, first bead of the box, beads in the box}, {kx, ky, kz, half}:
-  // the tile's offset within the bead's reserved tiles and which four of its
-  // eight z layers the block fills
+  // {bead, box, first bead of the box, beads in the box}, {kx, ky, kz, part}:
+  // the tile's offset within the bead's reserved tiles and which part
+  // (kTile / kSpreadParts z layers) of the tile the block fills
   const int4* spread_info;
   // (rho, u) of every node, written by the moment-recording stream-collide
   // variant only (segment recompute of the adjoint)

@@ -450,9 +450,9 @@ __device__ inline bool stencil_offset(int base, int origin, int extent, int N, i
   return false;
 }
 
-// One workgroup per half tile (four of the tile's eight z layers: twice the
-// workgroups, each adding only the markers whose stencils meet its half).
-// The markers whose stencils meet the half tile are compacted in (bead,
+// One workgroup per quarter tile (two of the tile's eight z layers: four
+// workgroups per tile, each adding only the markers whose stencils meet its
+// part).  The markers whose stencils meet the part are compacted in (bead,
 // marker) order; the thread that finds a marker stages its
 // stencil offset, its per-axis kernel weights and its force in LDS.  Entry e
 // goes to wavefront e % W (W wavefronts per workgroup), which adds the
@@ -493,13 +493,14 @@ __device__ inline bool covers(const SpreadBead& s, int tx, int ty, int tz, const
          pmod(tz - s.tlo[2], B.tz) < s.tcnt[2];
 }
 
-constexpr int kHalfLayers = kTile / 2;
-constexpr int kHalfNodes = kTile * kTile * kHalfLayers;  // 256
+static_assert(kTile % kSpreadParts == 0, "whole z layers per spreading part");
+constexpr int kPartLayers = kTile / kSpreadParts;  // z layers per spreading workgroup
+constexpr int kPartNodes = kTile * kTile * kPartLayers;  // 128
 
 template <int NW, int BS>
 __global__ __launch_bounds__(BS) void k_spread(Dev d) {
   constexpr int kSpreadWaves = BS / 64;
-  __shared__ float acc[kSpreadWaves][3][kHalfNodes];
+  __shared__ float acc[kSpreadWaves][3][kPartNodes];
   __shared__ SpreadEntry<NW> ent[BS];
   __shared__ int wave_cnt[kSpreadWaves];
   __shared__ SpreadBead sb[kSpreadBeads];
@@ -522,14 +523,14 @@ __global__ __launch_bounds__(BS) void k_spread(Dev d) {
   for (int i = 0; i < own; ++i)
     if (covers(spread_bead(d, sb, bead0, nb, i), tx, ty, tz, B)) return;  // an earlier bead owns this tile
   const int64_t n = *d.step + d.sub;
-  // this workgroup's half: z layers [oz, oz + ez) of the tile, ez <= 4
-  const int ox = tx * kTile, oy = ty * kTile, oz = tz * kTile + kHalfLayers * kk.w;
-  const int ex = min(kTile, B.nx - ox), ey = min(kTile, B.ny - oy), ez = min(kHalfLayers, B.nz - oz);
+  // this workgroup's part: z layers [oz, oz + ez) of the tile, ez <= kPartLayers
+  const int ox = tx * kTile, oy = ty * kTile, oz = tz * kTile + kPartLayers * kk.w;
+  const int ex = min(kTile, B.nx - ox), ey = min(kTile, B.ny - oy), ez = min(kPartLayers, B.nz - oz);
   if (kk.w == 0 && threadIdx.x == 0) d.stamp[B.tile0 + tx + B.tx * (ty + B.ty * tz)] = (int)n;
-  if (ez <= 0) return;  // the upper half of a short tile at the box's end holds no node
+  if (ez <= 0) return;  // an upper part of a short tile at the box's end holds no node
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
   for (int w = 0; w < kSpreadWaves; ++w)
-    for (int nd = threadIdx.x; nd < kHalfNodes; nd += BS) {
+    for (int nd = threadIdx.x; nd < kPartNodes; nd += BS) {
       acc[w][0][nd] = 0.0f;
       acc[w][1][nd] = 0.0f;
       acc[w][2][nd] = 0.0f;
@@ -619,7 +620,7 @@ __global__ __launch_bounds__(BS) void k_spread(Dev d) {
           const int lz = (E.off & 31) - 8 + sc;
           if ((unsigned)lx < (unsigned)ex && (unsigned)ly < (unsigned)ey && (unsigned)lz < (unsigned)ez) {
             const float w = E.w[0][sa] * E.w[1][sb_] * E.w[2][sc];
-            const int node = lx + kTile * (ly + kTile * lz);  // lz < ez <= 4
+            const int node = lx + kTile * (ly + kTile * lz);  // lz < ez <= kPartLayers
             acc[wave][0][node] += w * E.f[0];
             acc[wave][1][node] += w * E.f[1];
             acc[wave][2][node] += w * E.f[2];
@@ -629,7 +630,7 @@ __global__ __launch_bounds__(BS) void k_spread(Dev d) {
     }
   }
   __syncthreads();
-  for (int nd = threadIdx.x; nd < kHalfNodes; nd += BS) {
+  for (int nd = threadIdx.x; nd < kPartNodes; nd += BS) {
     const int lx = nd % kTile, ly = (nd / kTile) % kTile, lz = nd / (kTile * kTile);
     if (lx < ex && ly < ey && lz < ez) {
       float ax = 0, ay = 0, az = 0;

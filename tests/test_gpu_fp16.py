@@ -168,9 +168,11 @@ def test_pair_full_length_vs_stored_oracle(arrangement):
                          markers=float(np.abs(lat.markers() - ref["markers"]).max()))
         lat.close()
     print(arrangement, f"largest displacement {disp:.4e}:", res, flush=True)
-    # measured (collinear): FP32 centre 1.4e-4, field rel-L2 3.2e-6 and
-    # element-wise 8.8e-7, markers 9.5e-8; FP16 centre 1.1e-3, field 2.5e-4
-    # and 2.1e-4, markers 9.4e-7.  Bars about three times those.
+    # measured (collinear / side by side): FP32 centre 1.4e-4 / 1.4e-4, field
+    # rel-L2 3.2e-6 / 3.2e-6 and element-wise 8.5e-7 / 8.7e-7, markers
+    # 9.5e-8 / 1.0e-7; FP16 centre 0.86e-3 / 0.77e-3 (1.1e-3 before the
+    # force-free collision), field 2.4e-4 / 2.4e-4 and 1.3e-4 / 1.4e-4,
+    # markers 6.0e-7 / 4.7e-7.  Bars about three times the largest.
     assert res["fp32"]["centre"] < 5e-4 and res["fp32"]["u_l2"] < 1e-5 and res["fp32"]["u_max"] < 5e-6
     assert res["fp32"]["markers"] < 5e-7
     assert res["fp16"]["centre"] < 4e-3 and res["fp16"]["u_l2"] < 1e-3 and res["fp16"]["u_max"] < 1e-3
