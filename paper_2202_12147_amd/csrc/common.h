@@ -21,7 +21,16 @@ namespace lbmib {
 
 constexpr int kQ = 19;
 constexpr int kTile = 8;       // active-tile edge in nodes
-constexpr int kSpreadParts = 4;  // spreading workgroups per tile, each kTile / kSpreadParts z layers
+// Spreading workgroups per tile, each kTile / parts z layers: four for
+// handles of at most kWideBeads beads (wide 512-lane workgroups, latency of
+// the few of them dominates), two above (256-lane workgroups beside a bulk
+// launch that keeps the GPU busy)
+constexpr int kWideBeads = 32;
+constexpr int kSpreadPartsWide = 4;
+constexpr int kSpreadPartsNarrow = 2;
+__host__ __device__ constexpr int spread_parts(int nbeads) {
+  return nbeads <= kWideBeads ? kSpreadPartsWide : kSpreadPartsNarrow;
+}
 constexpr int kScBlock = 256;  // stream-collide threads per block
 // Near-block flags hold three step slots (step mod 3): the bead statistics of
 // step n mark slot n mod 3 while the bulk launch of step n - 1, which may
@@ -214,7 +223,7 @@ struct Dev {
   // per spread block (two per reserved tile of each bead), two int4:
   // {bead, box, first bead of the box, beads in the box}, {kx, ky, kz, part}:
   // the tile's offset within the bead's reserved tiles and which part
-  // (kTile / kSpreadParts z layers) of the tile the block fills
+  // (kTile / spread_parts(beads) z layers) of the tile the block fills
   const int4* spread_info;
   // (rho, u) of every node, written by the moment-recording stream-collide
   // variant only (segment recompute of the adjoint)

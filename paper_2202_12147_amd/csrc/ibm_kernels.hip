@@ -8,7 +8,8 @@
 //                     the Skalak, Kantor-Nelson bending and volume energies
 //                     (Sec. 2.2), gathered over the node's triangles and hinges
 //                     (no atomics), plus the node's 1/N_v share of the bead force.
-//   k_spread          one workgroup per 8x8x8 tile of a bead region: stages the
+//   k_spread          two or four workgroups per 8x8x8 tile of a bead region
+//                     (each a slab of its z layers): stages the
 //                     stencil weights of the markers touching the tile in LDS
 //                     (bead order, marker order) and accumulates
 //                     F(x) = sum_m f_m Delta(x - r_m) node by node (Eq.
@@ -45,7 +46,6 @@ constexpr int kStatsBlock = 256;
 constexpr int kStatsBlockWide = 1024;
 constexpr int kSpreadBlock = 256;
 constexpr int kSpreadBlockWide = 512;
-constexpr int kWideBeads = 32;  // at most this many beads: wide workgroups
 constexpr int kInterpBlock = 256;
 // Bead statistics: meshes of up to this many nodes (four refinements) are
 // staged in LDS for the volume sum; triangle ids loaded per round trip.
@@ -86,6 +86,62 @@ __device__ inline int stencil_base(double r) {
 
 __device__ inline double3 load_pos(const double* pos, int nm, int m) {
   return make_double3(pos[m], pos[nm + m], pos[2 * nm + m]);
+}
+
+// ---- wavefront reductions ---------------------------------------------------
+// Within rows of 16 lanes by DPP moves: pairs and quads by quad permutations,
+// then the mirrored half row and the mirrored row, after which every lane of
+// a row holds the row's total.  Each step is a register move of the ALU; a
+// shuffle routes every step through the LDS unit.
+constexpr int kDppXor1 = 0xB1;         // quad_perm [1, 0, 3, 2]
+constexpr int kDppXor2 = 0x4E;         // quad_perm [2, 3, 0, 1]
+constexpr int kDppHalfMirror = 0x141;  // lane i <- lane 7 - i of its half row
+constexpr int kDppMirror = 0x140;      // lane i <- lane 15 - i of its row
+
+template <int CTRL>
+__device__ inline float dpp_move(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ inline double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+enum { kRedSum, kRedMin, kRedMax };
+template <int OP, typename T>
+__device__ inline T red_op(T a, T b) {
+  if constexpr (OP == kRedSum) return a + b;
+  else if constexpr (OP == kRedMin) return fmin(a, b);  // a NaN operand is dropped
+  else return fmax(a, b);
+}
+
+// The reduction over each aligned group of L lanes (L a power of two up to
+// 64), the result in every lane of the group; the steps beyond a row of 16
+// are shuffles.
+template <int L, int OP = kRedSum, typename T>
+__device__ inline T group_reduce(T v) {
+  if constexpr (L >= 2) v = red_op<OP>(v, dpp_move<kDppXor1>(v));
+  if constexpr (L >= 4) v = red_op<OP>(v, dpp_move<kDppXor2>(v));
+  if constexpr (L >= 8) v = red_op<OP>(v, dpp_move<kDppHalfMirror>(v));
+  if constexpr (L >= 16) v = red_op<OP>(v, dpp_move<kDppMirror>(v));
+#pragma unroll
+  for (int s = 16; s < L; s <<= 1) v = red_op<OP>(v, __shfl_xor(v, s, 64));
+  return v;
+}
+
+// The reduction over the whole wavefront, the result in every lane: row
+// totals by DPP, then the four rows read out and combined in a fixed order.
+template <int OP>
+__device__ inline double wave_reduce(double v) {
+  v = group_reduce<16, OP>(v);
+  double r[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    r[k] = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 16 * k),
+                            __builtin_amdgcn_readlane(__double2loint(v), 16 * k));
+  return red_op<OP>(red_op<OP>(r[0], r[1]), red_op<OP>(r[2], r[3]));
 }
 
 // ---- block reductions -------------------------------------------------------
@@ -179,15 +235,12 @@ __global__ __launch_bounds__(BS) void k_bead_stats(Dev d, int mark_offset) {
     }
   }
 #pragma unroll
-  for (int s = 32; s > 0; s >>= 1) {
-#pragma unroll
-    for (int k = 0; k < 3; ++k) v[k] += __shfl_xor(v[k], s, 64);
-#pragma unroll
-    for (int k = 3; k < 6; ++k) v[k] = fmin(v[k], __shfl_xor(v[k], s, 64));
-#pragma unroll
-    for (int k = 6; k < 9; ++k) v[k] = fmax(v[k], __shfl_xor(v[k], s, 64));
-    v[9] += __shfl_xor(v[9], s, 64);
+  for (int k = 0; k < 3; ++k) {
+    v[k] = wave_reduce<kRedSum>(v[k]);
+    v[3 + k] = wave_reduce<kRedMin>(v[3 + k]);
+    v[6 + k] = wave_reduce<kRedMax>(v[6 + k]);
   }
+  v[9] = wave_reduce<kRedSum>(v[9]);
   if (lane == 0)
     for (int k = 0; k < NV; ++k) part[wave][k] = v[k];
   __syncthreads();
@@ -418,12 +471,9 @@ __global__ __launch_bounds__(256) void k_vertex_forces(Dev d) {
       fz = f.z;
     }
   }
-#pragma unroll
-  for (int s = kVertLanes / 2; s > 0; s >>= 1) {
-    fx += __shfl_xor(fx, s, 64);
-    fy += __shfl_xor(fy, s, 64);
-    fz += __shfl_xor(fz, s, 64);
-  }
+  fx = group_reduce<kVertLanes>(fx);
+  fy = group_reduce<kVertLanes>(fy);
+  fz = group_reduce<kVertLanes>(fz);
   if (m < d.nm && lane == 0) {
     const float inv = 1.0f / (float)nv;
     d.fm[m] = fx + (float)fb[0] * inv;
@@ -450,9 +500,9 @@ __device__ inline bool stencil_offset(int base, int origin, int extent, int N, i
   return false;
 }
 
-// One workgroup per quarter tile (two of the tile's eight z layers: four
-// workgroups per tile, each adding only the markers whose stencils meet its
-// part).  The markers whose stencils meet the part are compacted in (bead,
+// One workgroup per part of a tile (spread_parts: four parts of two z layers
+// for handles of few beads, two of four above; each workgroup adds only the
+// markers whose stencils meet its part).  Those markers are compacted in (bead,
 // marker) order; the thread that finds a marker stages its
 // stencil offset, its per-axis kernel weights and its force in LDS.  Entry e
 // goes to wavefront e % W (W wavefronts per workgroup), which adds the
@@ -493,12 +543,13 @@ __device__ inline bool covers(const SpreadBead& s, int tx, int ty, int tz, const
          pmod(tz - s.tlo[2], B.tz) < s.tcnt[2];
 }
 
-static_assert(kTile % kSpreadParts == 0, "whole z layers per spreading part");
-constexpr int kPartLayers = kTile / kSpreadParts;  // z layers per spreading workgroup
-constexpr int kPartNodes = kTile * kTile * kPartLayers;  // 128
 
-template <int NW, int BS>
+// PARTS workgroups per tile (spread_parts), each kTile / PARTS z layers
+template <int NW, int BS, int PARTS>
 __global__ __launch_bounds__(BS) void k_spread(Dev d) {
+  static_assert(kTile % PARTS == 0, "whole z layers per spreading part");
+  constexpr int kPartLayers = kTile / PARTS;
+  constexpr int kPartNodes = kTile * kTile * kPartLayers;
   constexpr int kSpreadWaves = BS / 64;
   __shared__ float acc[kSpreadWaves][3][kPartNodes];
   __shared__ SpreadEntry<NW> ent[BS];
@@ -674,12 +725,9 @@ __global__ __launch_bounds__(kInterpBlock) void k_interp_advance(Dev d) {
     uy = w * d.u[d.pstride + node];
     uz = w * d.u[2 * d.pstride + node];
   }
-#pragma unroll
-  for (int s = L / 2; s > 0; s >>= 1) {
-    ux += __shfl_xor(ux, s, 64);
-    uy += __shfl_xor(uy, s, 64);
-    uz += __shfl_xor(uz, s, 64);
-  }
+  ux = group_reduce<L>(ux);
+  uy = group_reduce<L>(uy);
+  uz = group_reduce<L>(uz);
   if (m < d.nm && lane == 0) {
     d.U[m] = ux;
     d.U[d.nm + m] = uy;
@@ -729,18 +777,19 @@ void launch_vertex_forces(const Dev& d, hipStream_t s) {
   hipLaunchKernelGGL(k_vertex_forces, dim3(blocks), dim3(256), 0, s, d);
 }
 
-template <int BS>
+template <int BS, int PARTS>
 static void launch_spread_bs(const Dev& d, hipStream_t s) {
-  if (d.width == 2) hipLaunchKernelGGL((k_spread<2, BS>), dim3(d.spread_blocks), dim3(BS), 0, s, d);
-  else if (d.width == 3) hipLaunchKernelGGL((k_spread<3, BS>), dim3(d.spread_blocks), dim3(BS), 0, s, d);
-  else hipLaunchKernelGGL((k_spread<4, BS>), dim3(d.spread_blocks), dim3(BS), 0, s, d);
+  if (d.width == 2) hipLaunchKernelGGL((k_spread<2, BS, PARTS>), dim3(d.spread_blocks), dim3(BS), 0, s, d);
+  else if (d.width == 3) hipLaunchKernelGGL((k_spread<3, BS, PARTS>), dim3(d.spread_blocks), dim3(BS), 0, s, d);
+  else hipLaunchKernelGGL((k_spread<4, BS, PARTS>), dim3(d.spread_blocks), dim3(BS), 0, s, d);
 }
 
+// the part count follows the same rule as the host's candidate-block table
 void launch_spread(const Dev& d, hipStream_t s) {
-  if (d.nbeads <= kWideBeads)
-    launch_spread_bs<kSpreadBlockWide>(d, s);
+  if (spread_parts(d.nbeads) == kSpreadPartsWide)
+    launch_spread_bs<kSpreadBlockWide, kSpreadPartsWide>(d, s);
   else
-    launch_spread_bs<kSpreadBlock>(d, s);
+    launch_spread_bs<kSpreadBlock, kSpreadPartsNarrow>(d, s);
 }
 
 void launch_interp_advance(const Dev& d, hipStream_t s) {

@@ -253,9 +253,10 @@ int upload(lbm_handle* h) {
     if (B.nbeads == 0) B.bead0 = (int)b;
     B.nbeads += 1;
   }
-  // spread candidate blocks, kSpreadParts per reserved tile of each bead (each
-  // kTile / kSpreadParts z layers): {bead, box, first bead of the box, beads
-  // of the box}, {tile offsets kx, ky, kz, part}
+  // spread candidate blocks, spread_parts(beads) per reserved tile of each
+  // bead (each kTile / parts z layers): {bead, box, first bead of the box,
+  // beads of the box}, {tile offsets kx, ky, kz, part}
+  const int parts = spread_parts((int)h->beads.size());
   std::vector<int> spread_info;
   for (size_t b = 0; b < h->beads.size(); ++b) {
     Bead& Bd = h->beads[b];
@@ -264,7 +265,7 @@ int upload(lbm_handle* h) {
     for (int kz = 0; kz < Bd.tiles_z; ++kz)
       for (int ky = 0; ky < Bd.tiles_y; ++ky)
         for (int kx = 0; kx < Bd.tiles_x; ++kx)
-          for (int part = 0; part < kSpreadParts; ++part) {
+          for (int part = 0; part < parts; ++part) {
             const int e[8] = {(int)b, Bd.box, B.bead0, B.nbeads, kx, ky, kz, part};
             spread_info.insert(spread_info.end(), e, e + 8);
           }
