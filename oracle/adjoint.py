@@ -4,7 +4,8 @@ An independent, plain PyTorch (CPU, float64) implementation of the forward
 step -- the same method and reading as the C oracle (see orc_sim.c): bead
 centres, driving and spring forces (Sec. 2.2), Skalak / Kantor-Nelson /
 volume membrane forces (Sec. 2.2), spreading (Eq. spreading), periodic
-streaming and Guo-forced BGK collision (Eqs. lbe, lbm:equilibrium),
+streaming and BGK collision with Guo or Shan-Chen forcing (Eqs. lbe,
+lbm:equilibrium, sc; the physical velocity (j + F/2)/rho in both),
 interpolation (Eq. interpolation) and forward-Euler advection -- written
 as differentiable tensor expressions.  The gradient of
 
@@ -84,7 +85,8 @@ class SwimmerModel:
         nx, ny, nz = self.shape
         self.N = nx * ny * nz
         self.tau = float(case["tau"])
-        assert case["forcing"] == 0, "gradient oracle implements Guo forcing"
+        self.forcing = int(case["forcing"])
+        assert self.forcing in (0, 1), "Guo (0) or Shan-Chen (1) forcing"
         self.width = int(case["width"])
         sw = case["swimmers"][0]
         self.sw = sw
@@ -254,14 +256,23 @@ class SwimmerModel:
         fs = self.stream(f).reshape(19, -1)
         rho = fs.sum(0)
         j = fs.t() @ self.cd  # [N, 3]
-        u = (j + 0.5 * F) / rho[:, None]
-        cu = u @ self.cd.t()  # [N, 19]
-        uu = (u * u).sum(1, keepdim=True)
-        feq = self.w * rho[:, None] * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu)
-        cF = F @ self.cd.t()
-        uF = (u * F).sum(1, keepdim=True)
-        src = (1.0 - 0.5 / self.tau) * self.w * (3.0 * (cF - uF) + 9.0 * cu * cF)
-        fo = fs.t() - (fs.t() - feq) / self.tau + src
+        u = (j + 0.5 * F) / rho[:, None]  # physical velocity, both forcings
+        if self.forcing == 0:
+            # Guo: the equilibrium at u plus the source term
+            cu = u @ self.cd.t()  # [N, 19]
+            uu = (u * u).sum(1, keepdim=True)
+            feq = self.w * rho[:, None] * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu)
+            cF = F @ self.cd.t()
+            uF = (u * F).sum(1, keepdim=True)
+            src = (1.0 - 0.5 / self.tau) * self.w * (3.0 * (cF - uF) + 9.0 * cu * cF)
+            fo = fs.t() - (fs.t() - feq) / self.tau + src
+        else:
+            # Shan-Chen (Eq. sc): the equilibrium at (j + tau F)/rho, no source
+            v = (j + self.tau * F) / rho[:, None]
+            cv = v @ self.cd.t()
+            vv = (v * v).sum(1, keepdim=True)
+            feq = self.w * rho[:, None] * (1.0 + 3.0 * cv + 4.5 * cv * cv - 1.5 * vv)
+            fo = fs.t() - (fs.t() - feq) / self.tau
         U = self.interp(r, u)
         return fo.t().reshape(19, nz, ny, nx), r + U
 

@@ -59,10 +59,31 @@ def test_forward_matches_c_oracle_other_kernels(width):
     assert np.abs(o.pops() - f.numpy()).max() < 1e-13
 
 
-def test_gradient_matches_finite_differences():
+def test_forward_matches_c_oracle_shan_chen():
+    """Shan-Chen forcing (Eq. sc: the equilibrium at (j + tau F)/rho, no
+    source term; interpolation of (j + F/2)/rho): the same markers and
+    populations as the C oracle after 30 steps, at tau 1 and 0.8."""
+    for tau in (1.0, 0.8):
+        case = workloads.adjoint_case(reduced=True)
+        case["forcing"] = workloads.SHAN_CHEN
+        case["tau"] = tau
+        model = adjoint.SwimmerModel(case)
+        th = [torch.tensor(v, dtype=torch.float64) for v in _theta(case)]
+        with torch.no_grad():
+            _, f, r = model.run(th, 30)
+        o = oracle_from(case)
+        o.step(30)
+        assert np.abs(o.markers() - r.numpy()).max() < 1e-12
+        assert np.abs(o.pops() - f.numpy()).max() < 1e-13
+
+
+@pytest.mark.parametrize("forcing", [workloads.GUO, workloads.SHAN_CHEN])
+def test_gradient_matches_finite_differences(forcing):
     """dJ/d(A, B, alpha, k) over 120 steps against central differences of the
-    C oracle's J with relative step 1e-4 (truncation ~1e-8, rounding ~1e-6)."""
+    C oracle's J with relative step 1e-4 (truncation ~1e-8, rounding ~1e-6),
+    for both forcing schemes."""
     case = workloads.adjoint_case(reduced=True)
+    case["forcing"] = forcing
     steps = 120
     J, g = adjoint.displacement_gradient(case, steps, checkpoint_every=40)
     assert abs(J - _c_objective(case, steps)) < 1e-13
