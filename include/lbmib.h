@@ -283,9 +283,9 @@ typedef struct {
  * per checkpoint; two segment buffers (the recompute of one segment runs
  * beside the reverse sweep of the next) of 28 bytes per node per segment
  * step ((rho, u) and the force density); six population sets.  The adjoint arithmetic is FP32 on the grid and FP64 on the markers
- * and parameter sums.  Single-box handles with FP32 storage and Guo forcing
- * only.  Errors: LBM_EINVAL (bad descriptor, batch, FP16 storage, Shan-Chen
- * forcing), LBM_ENOMEM, LBM_EDEVICE, LBM_EOVERFLOW. */
+ * and parameter sums.  Single-box handles with FP32 storage; Guo or
+ * Shan-Chen forcing (Sec. 2.1, Eq. sc).  Errors: LBM_EINVAL (bad descriptor,
+ * batch, FP16 storage), LBM_ENOMEM, LBM_EDEVICE, LBM_EOVERFLOW. */
 int lbm_adjoint(lbm_handle* h, const lbm_adjoint_desc* desc, double* J, double grad[4]);
 
 /* ---- checkpoint ---------------------------------------------------------------- */

@@ -471,7 +471,6 @@ int lbm_adjoint(lbm_handle* h, const lbm_adjoint_desc* desc, double* J, double g
     return h->fail(LBM_EINVAL, "adjoint objective: no such swimmer");
   if (h->boxes.size() != 1) return h->fail(LBM_EINVAL, "adjoint: single-box handles only");
   if (h->storage != LBM_FP32_SHIFTED) return h->fail(LBM_EINVAL, "adjoint: FP32 storage only");
-  if (h->boxes[0].forcing != kGuo) return h->fail(LBM_EINVAL, "adjoint: Guo forcing only");
   if (h->dev.uavg) return h->fail(LBM_ESTATE, "adjoint: stop the velocity average first (lbm_average_begin(h, 0))");
   int rc = rt::upload(h);
   if (rc) return rc;

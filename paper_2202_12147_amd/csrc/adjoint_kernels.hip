@@ -3,9 +3,9 @@
 //   k_adj_collide   every node: pulls the step-(n+1) population adjoints from
 //                   the downstream neighbours (the transpose of pull
 //                   streaming), forms the vector-Jacobian product of the
-//                   Guo-forced BGK collision (Eqs. lbe, lbm:equilibrium) with
-//                   respect to the pre-collision populations and the force
-//                   density, and stores both.
+//                   BGK collision with Guo or Shan-Chen forcing (Eqs. lbe,
+//                   lbm:equilibrium, sc) with respect to the pre-collision
+//                   populations and the force density, and stores both.
 //   k_adj_gather    a lane group per marker: transposed spreading
 //                   (lambda_f = sum_x lambda_F Delta) and the position
 //                   derivatives of the spreading and interpolation weights
@@ -135,29 +135,62 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(Dev d, Adj a, int nblock
     Pyz += w2 * (sef - sgh);
   }
   const float om = B.omega, sh = 1.0f - 0.5f * om;
-  const float P2ux = Pxx * ux + Pxy * uy + Pxz * uz;
-  const float P2uy = Pxy * ux + Pyy * uy + Pyz * uz;
-  const float P2uz = Pxz * ux + Pyz * uy + Pzz * uz;
-  const float P2Fx = Pxx * Fx + Pxy * Fy + Pxz * Fz;
-  const float P2Fy = Pxy * Fx + Pyy * Fy + Pyz * Fz;
-  const float P2Fz = Pxz * Fx + Pyz * Fy + Pzz * Fz;
-  const float uu = ux * ux + uy * uy + uz * uz;
-  const float aa = om * (P0 + 3.0f * (ux * Px + uy * Py + uz * Pz) + 4.5f * (ux * P2ux + uy * P2uy + uz * P2uz) -
-                         1.5f * uu * P0);
-  const float orho = om * rho;
-  const float bx = orho * (3.0f * Px + 9.0f * P2ux - 3.0f * ux * P0) + sh * (9.0f * P2Fx - 3.0f * Fx * P0) + lux;
-  const float by = orho * (3.0f * Py + 9.0f * P2uy - 3.0f * uy * P0) + sh * (9.0f * P2Fy - 3.0f * Fy * P0) + luy;
-  const float bz = orho * (3.0f * Pz + 9.0f * P2uz - 3.0f * uz * P0) + sh * (9.0f * P2Fz - 3.0f * Fz * P0) + luz;
   const float ir = 1.0f / rho;
-  if (forced) {
-    const float h = 0.5f * ir;
-    a.lF[base] = sh * (3.0f * Px - 3.0f * ux * P0 + 9.0f * P2ux) + h * bx;
-    a.lF[ps + base] = sh * (3.0f * Py - 3.0f * uy * P0 + 9.0f * P2uy) + h * by;
-    a.lF[2 * ps + base] = sh * (3.0f * Pz - 3.0f * uz * P0 + 9.0f * P2uz) + h * bz;
+  // lambda_f,i = (1 - omega) Lambda_i + a0 + bt.c_i
+  float a0, btx, bty, btz;
+  if (B.forcing == kShanChen) {
+    // Shan-Chen: the equilibrium at v = (j + tau F)/rho = u + (tau - 1/2) F/rho,
+    // no source term; u (interpolated, adjoint lambda_u) stays (j + F/2)/rho:
+    //   av  = omega [P0 + 3 v.P1 + 4.5 v.P2 v - 1.5 v.v P0]
+    //   bv  = omega rho [3 P1 + 9 P2 v - 3 v P0]
+    //   lambda_f,i = (1 - omega) Lambda_i + av + (bv.(c_i - v) + lambda_u.(c_i - u))/rho
+    //   lambda_F   = (tau bv + lambda_u / 2)/rho
+    const float kt = (B.tau - 0.5f) * ir;
+    const float vx = ux + kt * Fx, vy = uy + kt * Fy, vz = uz + kt * Fz;
+    const float P2vx = Pxx * vx + Pxy * vy + Pxz * vz;
+    const float P2vy = Pxy * vx + Pyy * vy + Pyz * vz;
+    const float P2vz = Pxz * vx + Pyz * vy + Pzz * vz;
+    const float vv = vx * vx + vy * vy + vz * vz;
+    const float av = om * (P0 + 3.0f * (vx * Px + vy * Py + vz * Pz) + 4.5f * (vx * P2vx + vy * P2vy + vz * P2vz) -
+                           1.5f * vv * P0);
+    const float orho = om * rho;
+    const float bvx = orho * (3.0f * Px + 9.0f * P2vx - 3.0f * vx * P0);
+    const float bvy = orho * (3.0f * Py + 9.0f * P2vy - 3.0f * vy * P0);
+    const float bvz = orho * (3.0f * Pz + 9.0f * P2vz - 3.0f * vz * P0);
+    if (forced) {
+      a.lF[base] = (B.tau * bvx + 0.5f * lux) * ir;
+      a.lF[ps + base] = (B.tau * bvy + 0.5f * luy) * ir;
+      a.lF[2 * ps + base] = (B.tau * bvz + 0.5f * luz) * ir;
+    }
+    btx = (bvx + lux) * ir;
+    bty = (bvy + luy) * ir;
+    btz = (bvz + luz) * ir;
+    a0 = av - ((bvx * vx + bvy * vy + bvz * vz) + (lux * ux + luy * uy + luz * uz)) * ir;
+  } else {
+    const float P2ux = Pxx * ux + Pxy * uy + Pxz * uz;
+    const float P2uy = Pxy * ux + Pyy * uy + Pyz * uz;
+    const float P2uz = Pxz * ux + Pyz * uy + Pzz * uz;
+    const float P2Fx = Pxx * Fx + Pxy * Fy + Pxz * Fz;
+    const float P2Fy = Pxy * Fx + Pyy * Fy + Pyz * Fz;
+    const float P2Fz = Pxz * Fx + Pyz * Fy + Pzz * Fz;
+    const float uu = ux * ux + uy * uy + uz * uz;
+    const float aa = om * (P0 + 3.0f * (ux * Px + uy * Py + uz * Pz) + 4.5f * (ux * P2ux + uy * P2uy + uz * P2uz) -
+                           1.5f * uu * P0);
+    const float orho = om * rho;
+    const float bx = orho * (3.0f * Px + 9.0f * P2ux - 3.0f * ux * P0) + sh * (9.0f * P2Fx - 3.0f * Fx * P0) + lux;
+    const float by = orho * (3.0f * Py + 9.0f * P2uy - 3.0f * uy * P0) + sh * (9.0f * P2Fy - 3.0f * Fy * P0) + luy;
+    const float bz = orho * (3.0f * Pz + 9.0f * P2uz - 3.0f * uz * P0) + sh * (9.0f * P2Fz - 3.0f * Fz * P0) + luz;
+    if (forced) {
+      const float h = 0.5f * ir;
+      a.lF[base] = sh * (3.0f * Px - 3.0f * ux * P0 + 9.0f * P2ux) + h * bx;
+      a.lF[ps + base] = sh * (3.0f * Py - 3.0f * uy * P0 + 9.0f * P2uy) + h * by;
+      a.lF[2 * ps + base] = sh * (3.0f * Pz - 3.0f * uz * P0 + 9.0f * P2uz) + h * bz;
+    }
+    btx = bx * ir;
+    bty = by * ir;
+    btz = bz * ir;
+    a0 = aa - (btx * ux + bty * uy + btz * uz);
   }
-  // lambda_f,i = (1 - omega) Lambda_i + alpha0 + beta.c_i
-  const float btx = bx * ir, bty = by * ir, btz = bz * ir;
-  const float a0 = aa - (btx * ux + bty * uy + btz * uz);
   const float k1 = 1.0f - om;
   const float cq[kQ] = {0.0f,       btx,        -btx,       bty,        -bty,       btz,        -btz,
                         btx + bty,  -btx - bty, btx - bty,  bty - btx,  btx + btz,  -btx - btz, btx - btz,
