@@ -243,9 +243,9 @@ void enqueue_recompute(lbm_handle* h, AdjWork& w, const AdjSet& St, const Dev& d
     hipEvent_t near_now = ev[2 + (i & 1)], near_prev = ev[2 + ((i + 1) & 1)];
     if (i > 0) launch_interp_advance(advect_view(dS, St, i - 1, nm), S2);
     const Dev dm = with_near(d, near_view(dS, w, St, i + 1));
-    launch_bead_stats(dm, 0, S2);
-    launch_vertex_forces(dm, S2);
+    launch_stats_forces(dm, 0, S2);
     launch_spread(dm, S2);
+    launch_marker_force_total(dm, dm.fm, S2);  // the step's total forces, read by the reverse sweep
     const Dev dr = with_near(d, near_view(dS, w, St, i));
     if (i > 0) (void)hipStreamWaitEvent(s, near_prev, 0);
     launch_stream_collide_mom(dr, kLaunchBulk, nblocks, s);
@@ -292,6 +292,7 @@ void enqueue_reverse(lbm_handle* h, AdjWork& w, const AdjSet& St, const Dev& dS,
     (void)hipEventRecord(bulk_now, s);
     Dev dl = d;
     dl.fm = w.lr32;
+    dl.spread_raw = 1;
     dl.F = w.lu;
     launch_spread(dl, S2);  // lambda_u = S(r_n) lambda_r(n+1), same tiles as F_n
     if (!first) (void)hipStreamWaitEvent(S2, bulk_prev, 0);

@@ -147,6 +147,14 @@ struct BeadState {
   int tlo[3], tcnt[3];  // region in tiles: first tile (in the box), count (periodic)
 };
 
+// Per-bead force terms of a step from its bead statistics (bead_terms.h):
+// volume pressure pv and the per-node share of the bead's driving + spring
+// force.
+struct BeadTerms {
+  float pv;
+  float share[3];
+};
+
 // Everything a kernel needs, passed by value.
 struct Dev {
   // lattice
@@ -166,7 +174,16 @@ struct Dev {
   // markers and meshes
   double* pos;           // [3][nm]
   float* U;              // [3][nm]
-  float* fm;             // [3][nm]
+  float* fm;             // [3][nm] total force on each marker (after the step)
+  // the force split by what it depends on, so the membrane part needs no
+  // bead statistics of the step: fmem = Skalak + bending, gvol = sum of the
+  // area vectors of the node's triangles; the total is
+  // fmem - pv gvol + (driving + spring force of the bead) / N_v
+  float* fmem;           // [3][nm]
+  float* gvol;           // [3][nm]
+  int spread_raw;        // 1: spread d.fm as given (the adjoint's lambda_r)
+  // bead terms of the step (bead_terms.h), kept by the spreading kernel
+  BeadTerms* bterms;     // [nbeads]
   int nm;
   int width;             // delta kernel support in nodes
   const Bead* beads;
@@ -207,7 +224,8 @@ struct Dev {
   int max_near, nsc, sc_bs;
   // nonzero in the near-block launch of the concurrent schedule: nbeads extra
   // workgroups mark the near blocks of the next step from the bead regions of
-  // this step (mark_near_blocks), off the bead-statistics kernel's path
+  // this step (mark_near_blocks), off the bead-statistics kernel's path, and
+  // further ones form each marker's total force (fm)
   int near_mark;
   // 1 when both population sets take at most kWriteThroughBytes: the
   // streaming stores are written through (stream_store) and the pulls are
@@ -269,7 +287,11 @@ hipError_t resolve_conserved_scratch(int device, double** out);
 // mark_offset: the near blocks of step (counter + sub + mark_offset) are
 // marked from the new bead regions; kNoMark: not marked.
 void launch_bead_stats(const Dev& d, int mark_offset, hipStream_t s);
-void launch_vertex_forces(const Dev& d, hipStream_t s);
+// bead statistics and the split membrane forces (independent of each other),
+// in one launch for handles of at most kWideBeads beads
+void launch_stats_forces(const Dev& d, int mark_offset, hipStream_t s);
+// total marker forces of step counter + sub from the split parts into out
+void launch_marker_force_total(const Dev& d, float* out, hipStream_t s);
 void launch_spread(const Dev& d, hipStream_t s);
 void launch_interp_advance(const Dev& d, hipStream_t s);
 void launch_bead_centres(const Dev& d, double* out, hipStream_t s);

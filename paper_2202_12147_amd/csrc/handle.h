@@ -85,7 +85,8 @@ struct lbm_handle {
   int64_t sc_table_cap = 0;       // stream-collide blocks at block 128: sum over boxes of ceil(n / 128)
   int64_t* d_step = nullptr;
   double* d_pos = nullptr;
-  float *d_U = nullptr, *d_fm = nullptr;
+  float *d_U = nullptr, *d_fm = nullptr, *d_fmem = nullptr, *d_gvol = nullptr;
+  lbmib::BeadTerms* d_bterms = nullptr;  // [beads]
   Bead* d_beads = nullptr;
   BeadState* d_bstate = nullptr;
   Swimmer* d_swimmers = nullptr;

@@ -1,13 +1,16 @@
 // Immersed-boundary and membrane kernels.
 //
-//   k_bead_stats      one workgroup per swimmer: bead centres (mean of the mesh
-//                     nodes, Fig. 1 caption), enclosed volumes, the node region
-//                     each bead's delta-kernel stencils can touch, and the
-//                     driving + spring force on each bead (Sec. 2.2).
-//   k_vertex_forces   one thread per mesh node: membrane forces f = -dW/dr of
-//                     the Skalak, Kantor-Nelson bending and volume energies
-//                     (Sec. 2.2), gathered over the node's triangles and hinges
-//                     (no atomics), plus the node's 1/N_v share of the bead force.
+//   k_bead_stats      one workgroup per bead: bead centres (mean of the mesh
+//                     nodes, Fig. 1 caption), enclosed volumes and the node
+//                     region each bead's delta-kernel stencils can touch.
+//   k_vertex_forces   32 lanes per mesh node: the membrane forces f = -dW/dr
+//                     of the Skalak and Kantor-Nelson bending energies and the
+//                     area-vector sum that the volume force scales (Sec. 2.2),
+//                     gathered over the node's triangles and hinges (no
+//                     atomics); no bead statistics needed.
+//   k_stats_forces    both of the above in one launch.
+//   (the spreading adds the bead terms: -pv times the area-vector sum and the
+//   node's 1/N_v share of the bead's driving and spring force, bead_terms.h)
 //   k_spread          two or four workgroups per 8x8x8 tile of a bead region
 //                     (each a slab of its z layers): stages the
 //                     stencil weights of the markers touching the tile in LDS
@@ -32,6 +35,7 @@
 // small difference of O(1) numbers decides the result (metric change of a
 // triangle, dihedral angle change of a hinge, volume change).
 #include "common.h"
+#include "bead_terms.h"
 #include "near_marks.h"
 
 namespace lbmib {
@@ -161,13 +165,12 @@ __device__ inline double block_sum(double v, double* sh) {
 // volume, reduced in FP64 with wavefront shuffles, and from the box the node
 // region the bead's stencils can touch (in 8^3 tiles).
 template <int NW, int BS>
-__global__ __launch_bounds__(BS) void k_bead_stats(Dev d, int mark_offset) {
+__device__ inline void bead_stats_block(const Dev& d, int b, int mark_offset) {
   constexpr int NWAVE = BS / 64;
   constexpr int NV = 10;  // sums x y z, min x y z, max x y z, volume
   __shared__ double part[NWAVE][NV];
   __shared__ int reg_lo[3], reg_hi[3];
   __shared__ double lpos[3][kStatsLdsVerts];
-  const int b = blockIdx.x;
   const Bead Bd = d.beads[b];
   const Box Bx = d.boxes[Bd.box];
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
@@ -303,17 +306,22 @@ __global__ __launch_bounds__(BS) void k_bead_stats(Dev d, int mark_offset) {
   if (mark_offset != kNoMark) mark_near_blocks(d, Bx, Bd.box, reg_lo, reg_hi, *d.step + d.sub + mark_offset);
 }
 
+template <int NW, int BS>
+__global__ __launch_bounds__(BS) void k_bead_stats(Dev d, int mark_offset) {
+  bead_stats_block<NW, BS>(d, blockIdx.x, mark_offset);
+}
+
 // ---- membrane forces ------------------------------------------------------------
-// Skalak + volume-penalty force on corner `corner` of triangle t.  With
+// Skalak force on corner `corner` of triangle t.  With
 // Delta = g - G0 (metric change, formed in FP64), I1 = G0^-1 : Delta,
 // I2 = (det g - det G0)/det G0 and the stress P = dW/dg written so that its
 // O(1) parts cancel analytically:
 //   P = ks A0/4 [(2 I1 + 2 C I2) G0^-1 + (2 C I2 - 2) adj(Delta)/det G0],
 // dW/de1 = 2 (P11 e1 + P12 e2), dW/de2 = 2 (P12 e1 + P22 e2), e_a = r_a - r_0.
-// Volume: f = -pv * (r_b - c) x (r_c - c) with (corner, b, c) counter-clockwise
-// and pv = kv (V - V0)/(6 V0).
+// The triangle's area vector (r1 - r0) x (r2 - r0), formed in FP64, goes to
+// `area`: the volume force of the corner is -pv times it (bead_terms.h).
 __device__ inline float3 triangle_corner(const Dev& d, const Bead& Bd, int t, int corner, int i0, int i1,
-                                         int i2, const double* c, float pv) {
+                                         int i2, float3& area) {
   const double3 p0 = load_pos(d.pos, d.nm, i0);
   const double3 p1 = load_pos(d.pos, d.nm, i1);
   const double3 p2 = load_pos(d.pos, d.nm, i2);
@@ -347,14 +355,8 @@ __device__ inline float3 triangle_corner(const Dev& d, const Bead& Bd, int t, in
     ca = -2.0f * (P11 + P12);
     cb = -2.0f * (P12 + P22);
   }
-  // the other two corners in counter-clockwise order
-  const double3 pb = corner == 0 ? p1 : (corner == 1 ? p2 : p0);
-  const double3 pc = corner == 0 ? p2 : (corner == 1 ? p0 : p1);
-  const float bx = (float)(pb.x - c[0]), by = (float)(pb.y - c[1]), bz = (float)(pb.z - c[2]);
-  const float qx = (float)(pc.x - c[0]), qy = (float)(pc.y - c[1]), qz = (float)(pc.z - c[2]);
-  return make_float3(-(ca * e1[0] + cb * e2[0]) - pv * (by * qz - bz * qy),
-                     -(ca * e1[1] + cb * e2[1]) - pv * (bz * qx - bx * qz),
-                     -(ca * e1[2] + cb * e2[2]) - pv * (bx * qy - by * qx));
+  area = make_float3((float)(e1y * e2z - e1z * e2y), (float)(e1z * e2x - e1x * e2z), (float)(e1x * e2y - e1y * e2x));
+  return make_float3(-(ca * e1[0] + cb * e2[0]), -(ca * e1[1] + cb * e2[1]), -(ca * e1[2] + cb * e2[2]));
 }
 
 // Kantor-Nelson bending force -kt sin(theta - theta0) d theta / d x_role on one
@@ -405,64 +407,34 @@ __device__ inline float3 bending_role(const Dev& d, const Bead& Bd, int h, int r
                      -dW * (fa * (float)nAz + fb * (float)nBz));
 }
 
-// Driving + spring force on bead `slot` of swimmer S at step n (Sec. 2.2):
-// f1 = A sin(w n + phi0) x, f3 = B sin(w n + phi0 + alpha) x, f2 = -f1 - f3,
-// springs f_o = -k (|R_o - R_2| - L) (R_o - R_2)/|R_o - R_2| on the outer
-// beads with the opposite force on the middle one.
-__device__ inline void bead_force(const Swimmer& S, int slot, int64_t n, const double* const* c, double* f) {
-  const double t = (double)n;
-  const double f1 = S.A * sin(S.omega * t + S.phi0);
-  const double f3 = S.B * sin(S.omega * t + S.phi0 + S.alpha);
-  f[0] = slot == 0 ? f1 : (slot == 2 ? f3 : -f1 - f3);
-  f[1] = 0;
-  f[2] = 0;
-  const double* R2 = c[1];
-  for (int sp = 0; sp < 2; ++sp) {
-    const int outer = sp == 0 ? 0 : 2;
-    if (slot != outer && slot != 1) continue;
-    const double* Ro = c[outer];
-    const double dx = Ro[0] - R2[0], dy = Ro[1] - R2[1], dz = Ro[2] - R2[2];
-    const double len = sqrt(dx * dx + dy * dy + dz * dz);
-    const double s = (slot == outer ? -1.0 : 1.0) * S.k[sp] * (len - S.L0[sp]) / len;
-    f[0] += s * dx;
-    f[1] += s * dy;
-    f[2] += s * dz;
-  }
-}
-
 // 32 lanes per mesh node: lanes 0..7 take the node's incident triangles
-// (Skalak + volume), lanes 8..31 the hinges it belongs to (its own edges and
-// the edges opposite it: bending); a fixed shuffle tree sums them, and lane 0
-// adds the node's 1/N_v share of the bead force (Sec. 2.2).
+// (Skalak force and area vector), lanes 8..31 the hinges it belongs to (its
+// own edges and the edges opposite it: bending); a fixed reduction tree sums
+// them.  The result is the bead-independent part of the node force
+// (bead_terms.h): the kernel reads no bead statistics, so it can run beside
+// the statistics of the same step.
 constexpr int kVertLanes = 32;
 constexpr int kVertTriLanes = 8;
-__global__ __launch_bounds__(256) void k_vertex_forces(Dev d) {
-  const int gid = blockIdx.x * 256 + threadIdx.x;
+template <int BS>
+__device__ inline void vertex_forces_block(const Dev& d, int blk) {
+  const int gid = blk * BS + threadIdx.x;
   const int m = gid / kVertLanes, lane = gid % kVertLanes;
-  float fx = 0, fy = 0, fz = 0;
-  double fb[3] = {0, 0, 0};
-  int nv = 1;
+  float fx = 0, fy = 0, fz = 0, gx = 0, gy = 0, gz = 0;
   if (m < d.nm) {
     // every load below depends only on this first round of per-marker and
     // per-lane tables, so the kernel makes two dependent trips to memory
     const int4 mi = d.marker_info[m];
     const int e = d.lane_elem[gid];
     const int4 v = d.lane_v[gid];
-    const Bead Bd = d.beads[mi.x];
-    nv = Bd.nv;
-    if (lane == 0) {
-      // the bead's driving and spring force from its swimmer's three centres
-      // (the beads of a swimmer are numbered consecutively from mi.w)
-      const BeadState* st = d.bstate + mi.w;
-      const double* c[3] = {st[0].c, st[1].c, st[2].c};
-      bead_force(d.swimmers[mi.z >> 2], mi.z & 3, *d.step + d.sub, c, fb);
-    }
     if (e >= 0) {
+      const Bead Bd = d.beads[mi.x];
       float3 f;
       if (lane < kVertTriLanes) {
-        const BeadState& st = d.bstate[mi.x];
-        const float pv = (float)(Bd.kv * (st.V - Bd.V0) / (6.0 * Bd.V0));
-        f = triangle_corner(d, Bd, e / 3, e % 3, v.x, v.y, v.z, st.c, pv);
+        float3 area;
+        f = triangle_corner(d, Bd, e / 3, e % 3, v.x, v.y, v.z, area);
+        gx = area.x;
+        gy = area.y;
+        gz = area.z;
       } else {
         f = bending_role(d, Bd, e / 4, e % 4, v);
       }
@@ -474,12 +446,42 @@ __global__ __launch_bounds__(256) void k_vertex_forces(Dev d) {
   fx = group_reduce<kVertLanes>(fx);
   fy = group_reduce<kVertLanes>(fy);
   fz = group_reduce<kVertLanes>(fz);
+  gx = group_reduce<kVertLanes>(gx);
+  gy = group_reduce<kVertLanes>(gy);
+  gz = group_reduce<kVertLanes>(gz);
   if (m < d.nm && lane == 0) {
-    const float inv = 1.0f / (float)nv;
-    d.fm[m] = fx + (float)fb[0] * inv;
-    d.fm[d.nm + m] = fy + (float)fb[1] * inv;
-    d.fm[2 * d.nm + m] = fz + (float)fb[2] * inv;
+    d.fmem[m] = fx;
+    d.fmem[d.nm + m] = fy;
+    d.fmem[2 * d.nm + m] = fz;
+    d.gvol[m] = gx;
+    d.gvol[d.nm + m] = gy;
+    d.gvol[2 * d.nm + m] = gz;
   }
+}
+
+__global__ __launch_bounds__(256) void k_vertex_forces(Dev d) { vertex_forces_block<256>(d, blockIdx.x); }
+
+// Bead statistics (the first nbeads workgroups) and the membrane forces (the
+// rest) of one step in one launch: neither reads what the other writes.
+template <int NW, int BS>
+__global__ __launch_bounds__(BS) void k_stats_forces(Dev d, int mark_offset) {
+  if ((int)blockIdx.x < d.nbeads)
+    bead_stats_block<NW, BS>(d, blockIdx.x, mark_offset);
+  else
+    vertex_forces_block<BS>(d, (int)blockIdx.x - d.nbeads);
+}
+
+// Total force on every marker of step counter + sub into out (observables,
+// the adjoint's recorded forces).
+__global__ __launch_bounds__(256) void k_marker_force_total(Dev d, float* out) {
+  const int m = blockIdx.x * 256 + threadIdx.x;
+  if (m >= d.nm) return;
+  const BeadTerms t = d.bterms[d.marker_info[m].x];
+  float f[3];
+  marker_total(d, m, t, f);
+  out[m] = f[0];
+  out[d.nm + m] = f[1];
+  out[2 * d.nm + m] = f[2];
 }
 
 // ---- spreading --------------------------------------------------------------------
@@ -526,16 +528,25 @@ struct SpreadEntry {
 constexpr int kSpreadBeads = 64;   // beads per box held in LDS (more: read from memory)
 constexpr int kSpreadRounds = 4;   // marker chunks loaded per round trip
 
-// Tile region and mesh range of bead i of the box (LDS copy or memory).
+// Tile region, mesh range and the force terms of the step (volume pressure,
+// per-node share of the driving + spring force) of bead i of the box (LDS
+// copy or memory).
 struct SpreadBead {
   int tlo[3], tcnt[3], first, nv;
+  BeadTerms t;
 };
 
-__device__ inline SpreadBead spread_bead(const Dev& d, const SpreadBead* sb, int bead0, int nb, int i) {
+__device__ inline SpreadBead make_spread_bead(const Dev& d, int b, int64_t n) {
+  const BeadState& s = d.bstate[b];
+  const Bead& q = d.beads[b];
+  SpreadBead r{{s.tlo[0], s.tlo[1], s.tlo[2]}, {s.tcnt[0], s.tcnt[1], s.tcnt[2]}, q.first, q.nv, {0.0f, {0.0f, 0.0f, 0.0f}}};
+  if (!d.spread_raw) r.t = bead_terms(d, b, n);
+  return r;
+}
+
+__device__ inline SpreadBead spread_bead(const Dev& d, const SpreadBead* sb, int bead0, int nb, int i, int64_t n) {
   if (nb <= kSpreadBeads) return sb[i];
-  const BeadState& s = d.bstate[bead0 + i];
-  const Bead& q = d.beads[bead0 + i];
-  return SpreadBead{{s.tlo[0], s.tlo[1], s.tlo[2]}, {s.tcnt[0], s.tcnt[1], s.tcnt[2]}, q.first, q.nv};
+  return make_spread_bead(d, bead0 + i, n);
 }
 
 __device__ inline bool covers(const SpreadBead& s, int tx, int ty, int tz, const Box& B) {
@@ -561,19 +572,18 @@ __global__ __launch_bounds__(BS) void k_spread(Dev d) {
   const int b = info.x, bead0 = info.z, nb = info.w, own = b - bead0;
   // round trip 2: the box and every bead of the box
   const Box B = d.boxes[info.y];
+  const int64_t n = *d.step + d.sub;
   if (nb <= kSpreadBeads)
-    for (int i = threadIdx.x; i < nb; i += BS) {
-      const BeadState& st = d.bstate[bead0 + i];
-      const Bead& q = d.beads[bead0 + i];
-      sb[i] = SpreadBead{{st.tlo[0], st.tlo[1], st.tlo[2]}, {st.tcnt[0], st.tcnt[1], st.tcnt[2]}, q.first, q.nv};
-    }
+    for (int i = threadIdx.x; i < nb; i += BS) sb[i] = make_spread_bead(d, bead0 + i, n);
   __syncthreads();
-  const SpreadBead S = spread_bead(d, sb, bead0, nb, own);
+  const SpreadBead S = spread_bead(d, sb, bead0, nb, own, n);
+  // the first candidate block of each bead keeps its terms for the total
+  // marker forces formed later in the step
+  if (!d.spread_raw && threadIdx.x == 0 && kk.x == 0 && kk.y == 0 && kk.z == 0 && kk.w == 0) d.bterms[b] = S.t;
   if (kk.x >= S.tcnt[0] || kk.y >= S.tcnt[1] || kk.z >= S.tcnt[2]) return;
   const int tx = pmod(S.tlo[0] + kk.x, B.tx), ty = pmod(S.tlo[1] + kk.y, B.ty), tz = pmod(S.tlo[2] + kk.z, B.tz);
   for (int i = 0; i < own; ++i)
-    if (covers(spread_bead(d, sb, bead0, nb, i), tx, ty, tz, B)) return;  // an earlier bead owns this tile
-  const int64_t n = *d.step + d.sub;
+    if (covers(spread_bead(d, sb, bead0, nb, i, n), tx, ty, tz, B)) return;  // an earlier bead owns this tile
   // this workgroup's part: z layers [oz, oz + ez) of the tile, ez <= kPartLayers
   const int ox = tx * kTile, oy = ty * kTile, oz = tz * kTile + kPartLayers * kk.w;
   const int ex = min(kTile, B.nx - ox), ey = min(kTile, B.ny - oy), ez = min(kPartLayers, B.nz - oz);
@@ -610,9 +620,15 @@ __global__ __launch_bounds__(BS) void k_spread(Dev d) {
         px[r] = d.pos[m];
         py[r] = d.pos[d.nm + m];
         pz[r] = d.pos[2 * d.nm + m];
-        fx[r] = d.fm[m];
-        fy[r] = d.fm[d.nm + m];
-        fz[r] = d.fm[2 * d.nm + m];
+        if (d.spread_raw) {
+          fx[r] = d.fm[m];
+          fy[r] = d.fm[d.nm + m];
+          fz[r] = d.fm[2 * d.nm + m];
+        } else {
+          fx[r] = total_force(d.fmem[m], d.gvol[m], Q.t.pv, Q.t.share[0]);
+          fy[r] = total_force(d.fmem[d.nm + m], d.gvol[d.nm + m], Q.t.pv, Q.t.share[1]);
+          fz[r] = total_force(d.fmem[2 * d.nm + m], d.gvol[2 * d.nm + m], Q.t.pv, Q.t.share[2]);
+        }
       }
       ++nr;
       // advance to the next chunk: the rest of this bead, else the next
@@ -621,7 +637,7 @@ __global__ __launch_bounds__(BS) void k_spread(Dev d) {
       if (c0 >= Q.nv) {
         c0 = 0;
         for (++cb; cb < nb; ++cb) {
-          Q = spread_bead(d, sb, bead0, nb, cb);
+          Q = spread_bead(d, sb, bead0, nb, cb, n);
           if (covers(Q, tx, ty, tz, B)) break;
         }
       }
@@ -772,9 +788,25 @@ void launch_bead_stats(const Dev& d, int mark_offset, hipStream_t s) {
     launch_stats_bs<kStatsBlock>(d, mark_offset, s);
 }
 
-void launch_vertex_forces(const Dev& d, hipStream_t s) {
-  const int blocks = (int)(((int64_t)d.nm * kVertLanes + 255) / 256);
-  hipLaunchKernelGGL(k_vertex_forces, dim3(blocks), dim3(256), 0, s, d);
+// Few beads: statistics and forces in one launch of wide workgroups; many
+// beads: two launches (the statistics' LDS would otherwise cap the force
+// workgroups per CU).
+void launch_stats_forces(const Dev& d, int mark_offset, hipStream_t s) {
+  if (d.nbeads <= kWideBeads) {
+    constexpr int BS = kStatsBlockWide;
+    const int grid = d.nbeads + (int)(((int64_t)d.nm * kVertLanes + BS - 1) / BS);
+    if (d.width == 2) hipLaunchKernelGGL((k_stats_forces<2, BS>), dim3(grid), dim3(BS), 0, s, d, mark_offset);
+    else if (d.width == 3) hipLaunchKernelGGL((k_stats_forces<3, BS>), dim3(grid), dim3(BS), 0, s, d, mark_offset);
+    else hipLaunchKernelGGL((k_stats_forces<4, BS>), dim3(grid), dim3(BS), 0, s, d, mark_offset);
+  } else {
+    launch_stats_bs<kStatsBlock>(d, mark_offset, s);
+    const int blocks = (int)(((int64_t)d.nm * kVertLanes + 255) / 256);
+    hipLaunchKernelGGL(k_vertex_forces, dim3(blocks), dim3(256), 0, s, d);
+  }
+}
+
+void launch_marker_force_total(const Dev& d, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_marker_force_total, dim3((d.nm + 255) / 256), dim3(256), 0, s, d, out);
 }
 
 template <int BS, int PARTS>

@@ -19,6 +19,7 @@
 #include <hip/hip_fp16.h>
 
 #include "common.h"
+#include "bead_terms.h"
 #include "near_marks.h"
 
 #include <hip/hip_ext.h>
@@ -398,6 +399,20 @@ __global__ __launch_bounds__(BS) void k_stream_collide(Dev d, int remap, int nbl
   const int pp = (int)(pn & 1), pf = near_slot(pn);
   const bool avg = AVG && avg_sampled(d, n);
   if constexpr (MODE == kScActive) {
+    if ((int)blockIdx.x >= d.max_near + d.nbeads) {
+      // the total force of each marker at step n (the observable; the
+      // spreading formed the same sums from the split parts)
+      const int m = ((int)blockIdx.x - d.max_near - d.nbeads) * BS + (int)threadIdx.x;
+      if (m < d.nm) {
+        const BeadTerms t = d.bterms[d.marker_info[m].x];
+        float f[3];
+        marker_total(d, m, t, f);
+        d.fm[m] = f[0];
+        d.fm[d.nm + m] = f[1];
+        d.fm[2 * d.nm + m] = f[2];
+      }
+      return;
+    }
     if ((int)blockIdx.x >= d.max_near) {
       // the near blocks of step n + 1 around bead blockIdx.x - max_near, from
       // the bead region its statistics kernel found at step n
@@ -669,7 +684,7 @@ template <int ST, int MODE, bool AVG, bool NTLD>
 static void launch_sc_mode(const Dev& d, int block, int nblocks, int remap, int resident, int ncu,
                            hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   int grid = remap ? (nblocks + 7) / 8 * 8 : nblocks;
-  if (MODE == kScActive) grid = d.max_near + (d.near_mark ? d.nbeads : 0);
+  if (MODE == kScActive) grid = d.max_near + (d.near_mark ? d.nbeads + (d.nm + block - 1) / block : 0);
   if (MODE == kScBulk && resident > 0)
     grid = remap ? std::min(grid, ncu * resident) / 8 * 8 : std::min(grid, ncu * resident);
   if (MODE != kScBulk) resident = 0;

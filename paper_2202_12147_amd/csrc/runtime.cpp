@@ -279,6 +279,9 @@ int upload(lbm_handle* h) {
   h->d_pos = h->alloc<double>(3 * (size_t)nm, rc);
   h->d_U = h->alloc<float>(3 * (size_t)nm, rc);
   h->d_fm = h->alloc<float>(3 * (size_t)nm, rc);
+  h->d_fmem = h->alloc<float>(3 * (size_t)nm, rc);
+  h->d_gvol = h->alloc<float>(3 * (size_t)nm, rc);
+  h->d_bterms = h->alloc<BeadTerms>(h->beads.size(), rc);
   h->d_beads = h->alloc<Bead>(h->beads.size(), rc);
   h->d_bstate = h->alloc<BeadState>(h->beads.size(), rc);
   h->d_swimmers = h->alloc<Swimmer>(h->swimmers.size(), rc);
@@ -309,6 +312,9 @@ int upload(lbm_handle* h) {
   if (rc == LBM_OK && nm > 0) {
     rc = h->hip(hipMemset(h->d_U, 0, sizeof(float) * 3 * nm), "hipMemset");
     if (rc == LBM_OK) rc = h->hip(hipMemset(h->d_fm, 0, sizeof(float) * 3 * nm), "hipMemset");
+    if (rc == LBM_OK) rc = h->hip(hipMemset(h->d_fmem, 0, sizeof(float) * 3 * nm), "hipMemset");
+    if (rc == LBM_OK) rc = h->hip(hipMemset(h->d_gvol, 0, sizeof(float) * 3 * nm), "hipMemset");
+    if (rc == LBM_OK) rc = h->hip(hipMemset(h->d_bterms, 0, sizeof(BeadTerms) * h->beads.size()), "hipMemset");
   }
   put(h->d_beads, h->beads.data(), sizeof(Bead) * h->beads.size());
   {
@@ -350,6 +356,10 @@ int upload(lbm_handle* h) {
   d.pos = h->d_pos;
   d.U = h->d_U;
   d.fm = h->d_fm;
+  d.fmem = h->d_fmem;
+  d.gvol = h->d_gvol;
+  d.spread_raw = 0;
+  d.bterms = h->d_bterms;
   d.nm = nm;
   d.beads = h->d_beads;
   d.nbeads = (int)h->beads.size();
@@ -430,9 +440,9 @@ void enqueue_steps(lbm_handle* h, int64_t count) {
     // serial order: the immersed-boundary chain, then the full grid
     for (int64_t i = 0; i < count; ++i) {
       d.sub = (int)i;
-      launch_bead_stats(d, 0, h->stream);
-      launch_vertex_forces(d, h->stream);
+      launch_stats_forces(d, 0, h->stream);
       launch_spread(d, h->stream);
+      launch_marker_force_total(d, d.fm, h->stream);
       hipEvent_t e0, e1;
       timing_pair(h, &e0, &e1);
       launch_stream_collide(d, h->storage, kLaunchAll, h->sc_block, h->sc_blocks, h->sc_remap, 0, h->ncu, h->stream,
@@ -456,9 +466,8 @@ void enqueue_steps(lbm_handle* h, int64_t count) {
     hipEvent_t ev_bulk = h->step_events[2 * (i % kGraphChunk)], ev_near = h->step_events[2 * (i % kGraphChunk) + 1];
     d.sub = (int)i;
     if (i > 0) launch_interp_advance(d, h->side);
-    launch_bead_stats(d, kNoMark, h->side);  // the near-block launch marks the next step's blocks
-    launch_vertex_forces(d, h->side);
-    launch_spread(d, h->side);
+    launch_stats_forces(d, kNoMark, h->side);  // the near-block launch marks the next step's blocks
+    launch_spread(d, h->side);                 // and forms the markers' total forces
     if (prev_near) (void)hipStreamWaitEvent(h->stream, prev_near, 0);
     hipEvent_t e0, e1;
     timing_pair(h, &e0, &e1);
@@ -874,6 +883,8 @@ int lbm_batch_swimmer_add(lbm_handle* h, int32_t box, const lbm_bead_desc beads[
                            (int)h->beads.size() - k};
       h->marker_info.insert(h->marker_info.end(), info, info + 4);
     }
+    // bead_terms (device) relies on swimmer s owning beads 3s .. 3s + 2
+    if ((int)h->beads.size() != 3 * (int)h->swimmers.size() + k) return h->fail(LBM_ESTATE, "bead numbering");
     S.bead[k] = (int)h->beads.size();
     h->beads.push_back(b);
     h->nm += nv;

@@ -192,7 +192,8 @@ hipError_t resolve_conserved_scratch(int, double** out) {
   return hipSuccess;
 }
 void launch_bead_stats(const Dev&, int, hipStream_t s) { check(s, "launch"); }
-void launch_vertex_forces(const Dev&, hipStream_t s) { check(s, "launch"); }
+void launch_stats_forces(const Dev&, int, hipStream_t s) { check(s, "launch"); }
+void launch_marker_force_total(const Dev&, float*, hipStream_t s) { check(s, "launch"); }
 void launch_spread(const Dev&, hipStream_t s) { check(s, "launch"); }
 void launch_interp_advance(const Dev&, hipStream_t s) { check(s, "launch"); }
 void launch_bead_centres(const Dev&, double* out, hipStream_t s) {
