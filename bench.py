@@ -281,21 +281,24 @@ def kernels_section(lbmib):
     return out
 
 
-def paper_length_section(lbmib, wl, periods, out_dir=None):
-    """The paper's single-swimmer run over `periods` actuation periods of
-    2e4 steps on the 1024x256x256 box (workloads.paper_run): the swimmer
-    velocity of each period (Eq. vel_swim), the Reynolds numbers of the
-    swimmer (v_cm * 2 L / nu) and of the fastest bead (largest bead speed
-    over the last period * 2 a / nu), and the velocity field averaged over
-    the last period (Figs. 3, 6, 9), saved downsampled when out_dir is set."""
+def paper_length_section(lbmib, wl, periods, out_dir=None, arrangement=None, distance=None, v_ref=None):
+    """The paper's runs over `periods` actuation periods of 2e4 steps on the
+    1024x256x256 box (workloads.paper_run): one swimmer, or a pair one behind
+    the other / side by side at a given distance of their middle beads.  Per
+    period and swimmer the centre velocity (Eq. vel_swim); the Reynolds
+    numbers of the swimmer (v_cm * 2 L / nu) and of the fastest bead (largest
+    bead speed over the last period * 2 a / nu); with v_ref (a single
+    swimmer's velocity) the relative change of each swimmer's velocity over
+    the last period (Eq. inc); and the velocity field averaged over the last
+    period (Figs. 3, 6, 9), saved downsampled when out_dir is set."""
     import numpy as np
-    case = wl.paper_run()
+    case = wl.paper_run(arrangement, distance)
     sw = case["swimmers"][0]
     T = int(case["period"])
     nu = (case["tau"] - 0.5) / 3.0
     lat = lbmib.from_workload(case)
     lat.set_stream_collide_launch(*BOX_LAUNCH)
-    X = [lat.swimmer_centres()[0].copy()]
+    X = [lat.swimmer_centres().copy()]
     per_period, bead_speed = [], 0.0
     t0 = time.perf_counter()
     chunk = 500
@@ -310,28 +313,34 @@ def paper_length_section(lbmib, wl, periods, out_dir=None):
                 R = lat.bead_centres()
                 bead_speed = max(bead_speed, float(np.abs(R - R_prev).max()) / chunk)
                 R_prev = R
-        X.append(lat.swimmer_centres()[0].copy())
-        v = (X[-1] - X[-2]) / T
-        per_period.append([float(c) for c in v])
-        print(f"paper run: period {p + 1}/{periods}: v_cm {v[0]:.6e} l.u./step "
-              f"({time.perf_counter() - t0:.0f} s)", flush=True)
+        X.append(lat.swimmer_centres().copy())
+        v = (X[-1] - X[-2]) / T  # [swimmer, 3]
+        per_period.append(v)
+        print(f"paper run: period {p + 1}/{periods}: v_cm " + " ".join(f"{vs[0]:.6e}" for vs in v) +
+              f" l.u./step ({time.perf_counter() - t0:.0f} s)", flush=True)
     avg, count = lat.average_velocity()
     lat.average_begin(0)
     L = 2.0 * float(sw["L0"][0])
     a = float(sw["radius"][0])
-    v_last = per_period[-1][0]
+    v_last = per_period[-1][:, 0]
     res = {"workload": case["name"], "periods": periods, "period_steps": T,
            "forcing": "shan-chen", "tau": case["tau"], "nu": nu,
-           "v_cm_per_period": [v[0] for v in per_period],
-           "v_cm_yz_last": per_period[-1][1:],
-           "v_ref": v_last, "Re_swim": abs(v_last) * L / nu,
+           "swimmer_x0": [float(x[0]) for x in X[0]],
+           "v_cm_per_period": [[float(vs[0]) for vs in v] for v in per_period],
+           "v_cm_yz_last": [[float(c) for c in vs[1:]] for vs in per_period[-1]],
+           "v_last": [float(x) for x in v_last], "Re_swim": float(np.abs(v_last).max()) * L / nu,
            "bead_speed_max_last_period": bead_speed, "Re_bead": bead_speed * 2.0 * a / nu,
            "mean_field_samples": count, "mean_field_max_abs": float(np.abs(avg).max()),
            "seconds": round(time.perf_counter() - t0, 1)}
+    if arrangement is None:
+        res["v_ref"] = float(v_last[0])
+    if v_ref:
+        res["v_delta_last"] = [float((v - v_ref) / v_ref) for v in v_last]
     if out_dir:
         os.makedirs(out_dir, exist_ok=True)
-        np.save(os.path.join(out_dir, "paper_run_mean_u_sub4.npy"), avg[:, ::4, ::4, ::4].astype(np.float32))
-        np.save(os.path.join(out_dir, "paper_run_mean_u_midplane.npy"), avg[:, avg.shape[1] // 2].astype(np.float32))
+        tag = "paper_run" if arrangement is None else f"paper_pair_{arrangement}_{distance:g}"
+        np.save(os.path.join(out_dir, f"{tag}_mean_u_sub4.npy"), avg[:, ::4, ::4, ::4].astype(np.float32))
+        np.save(os.path.join(out_dir, f"{tag}_mean_u_midplane.npy"), avg[:, avg.shape[1] // 2].astype(np.float32))
     return res
 
 
@@ -350,6 +359,12 @@ def main():
     ap.add_argument("--paper-length", type=int, default=0, metavar="PERIODS",
                     help="only the paper's single-swimmer run over PERIODS periods of 2e4 steps")
     ap.add_argument("--paper-out", default=None, help="directory for the paper run's averaged field")
+    ap.add_argument("--paper-pair", default=None, choices=["collinear", "side"],
+                    help="with --paper-length: two swimmers one behind the other or side by side")
+    ap.add_argument("--paper-distance", type=float, default=144.0,
+                    help="with --paper-pair: distance of the middle beads (lattice units)")
+    ap.add_argument("--paper-vref", type=float, default=None,
+                    help="with --paper-pair: a single swimmer's velocity, for the relative changes")
     ap.add_argument("--main-only", action="store_true",
                     help="skip the fp16, batch, adjoint and paper-box sections (counter runs)")
     args = ap.parse_args()
@@ -373,8 +388,9 @@ def main():
               flush=True)
         return
     if args.paper_length:
-        print(json.dumps({"paper_length": paper_length_section(lbmib, wl, args.paper_length, args.paper_out)}),
-              flush=True)
+        print(json.dumps({"paper_length": paper_length_section(
+            lbmib, wl, args.paper_length, args.paper_out, args.paper_pair,
+            args.paper_distance if args.paper_pair else None, args.paper_vref)}), flush=True)
         return
     case = wl.single_128(seed=0)
     nodes = case["shape"][0] * case["shape"][1] * case["shape"][2]

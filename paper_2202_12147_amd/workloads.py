@@ -149,18 +149,33 @@ def paper_moduli_case(adjoint=False):
                                   **PAPER_MODULI)])
 
 
-def paper_run():
+def paper_run(arrangement=None, distance=None):
     """The paper's single-swimmer run (Sec. 3): 1024x256x256 fully periodic
     box, tau 1 (mu = 1/6), Shan-Chen forcing as in the paper, radius-5 beads
     with the paper's moduli (refined twice, as in paper_moduli_case), rest
     length 36, k = 0.02, A = B = 5e-3 (the printed A = 1e-1 contradicts the
     bead Reynolds number the paper reports), T = 2e4, alpha = pi/2, 3-point
     kernel (the two-point kernel diverges within 500 steps with these
-    moduli, also in the oracle); at least 12 periods to stationarity."""
-    return dict(name="paper run 1024x256x256", shape=(1024, 256, 256), tau=1.0, forcing=SHAN_CHEN,
-                width=3, steps=12 * 20000, period=20000,
-                swimmers=[swimmer((512, 128, 128), 36.0, radius=5.0, level=2, k=0.02, A=5e-3, T=2e4,
-                                  alpha=math.pi / 2, **PAPER_MODULI)])
+    moduli, also in the oracle); at least 12 periods to stationarity.
+
+    arrangement "collinear" (Sec. 3.2) or "side" (Sec. 3.3): two identical,
+    in-phase swimmers whose middle beads are `distance` apart along x (one
+    behind the other) or along y (side by side), centred in the box."""
+    def one(mid):
+        return swimmer(mid, 36.0, radius=5.0, level=2, k=0.02, A=5e-3, T=2e4, alpha=math.pi / 2, **PAPER_MODULI)
+    if arrangement is None:
+        swimmers, name = [one((512, 128, 128))], "paper run 1024x256x256"
+    else:
+        h = 0.5 * float(distance)
+        if arrangement == "collinear":
+            mids = [(512 - h, 128, 128), (512 + h, 128, 128)]
+        elif arrangement == "side":
+            mids = [(512, 128 - h, 128), (512, 128 + h, 128)]
+        else:
+            raise ValueError(arrangement)
+        swimmers, name = [one(m) for m in mids], f"paper pair run 1024x256x256, {arrangement}, d = {distance:g}"
+    return dict(name=name, shape=(1024, 256, 256), tau=1.0, forcing=SHAN_CHEN, width=3, steps=12 * 20000,
+                period=20000, swimmers=swimmers)
 
 
 def random_deviation(shape, seed=0, eps=1e-4, modes=3):
