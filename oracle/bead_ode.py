@@ -88,7 +88,8 @@ class BeadSwimmers:
         if self.tensor == "oseen":
             T = oseen(r, self.mu)
         else:
-            T = rotne_prager(r, self.mu, self.a[:, None])
+            # radius of the bead the flow acts on (row i), one per tensor
+            T = rotne_prager(r, self.mu, self.a[:, None, None, None])
         T[np.arange(n), np.arange(n)] = 0.0
         return T
 

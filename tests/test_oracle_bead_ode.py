@@ -92,3 +92,48 @@ def test_zero_delay_equals_no_delay():
     a.run(300, 1.0)
     b.run(300, 1.0)
     np.testing.assert_allclose(a.R, b.R, rtol=0, atol=1e-9)
+
+
+def test_pair_tensors_closed_form():
+    """Two swimmers of different bead radii on one axis: every off-diagonal
+    3x3 block is the textbook tensor for that separation, with the radius of
+    the bead the flow acts on (row bead) in the Rotne-Prager correction:
+    along the axis 2 (1 - 2a^2/(3r^2)) / (8 pi mu r), across it
+    (1 + 2a^2/(3r^2)) / (8 pi mu r); Oseen is the a = 0 case."""
+    mu = 1.0 / 6.0
+    s1 = _swimmer(radius=0.5, L=10.0)
+    s2 = wl.swimmer((100.0, 0.0, 0.0), 10.0, radius=2.0, k=0.05, A=1e-5, T=400.0, alpha=math.pi / 2)
+    for tensor in ("oseen", "rotne_prager"):
+        m = bead_ode.BeadSwimmers([s1, s2], mu=mu, tensor=tensor)
+        T = m._tensors(m.R, m.R)
+        assert T.shape == (6, 6, 3, 3)
+        for i in range(6):
+            for j in range(6):
+                if i == j:
+                    assert np.abs(T[i, j]).max() == 0.0
+                    continue
+                r = abs(m.R[i, 0] - m.R[j, 0])
+                c = 2.0 * m.a[i] ** 2 / (3.0 * r * r) if tensor == "rotne_prager" else 0.0
+                want = np.diag([2.0 * (1.0 - c), 1.0 + c, 1.0 + c]) / (8.0 * math.pi * mu * r)
+                np.testing.assert_allclose(T[i, j], want, rtol=1e-13, atol=0)
+
+
+@pytest.mark.parametrize("tensor", ["oseen", "rotne_prager"])
+def test_pair_limits_and_symmetry(tensor):
+    """Two identical in-phase swimmers: side by side, the mirror plane between
+    them makes their speeds equal; far apart (separation 1e4 L) each swims
+    as if alone; listing them in the other order changes nothing."""
+    mu, T, dt = 1.0 / 6.0, 400.0, 2.0
+
+    def sw(x, y):
+        return wl.swimmer((x, y, 0.0), 50.0, radius=2.0, k=0.05, A=2e-3, T=T, alpha=math.pi / 2)
+
+    alone = bead_ode.period_velocity(bead_ode.BeadSwimmers([sw(0, 0)], mu, tensor), T, 3, dt)[-1, 0]
+    side = bead_ode.period_velocity(bead_ode.BeadSwimmers([sw(0, -40), sw(0, 40)], mu, tensor), T, 3, dt)[-1]
+    assert abs(side[0] - side[1]) <= 1e-12 * abs(alone)
+    assert abs(side[0] - alone) > 1e-3 * abs(alone)  # and the neighbour does matter
+    far = bead_ode.period_velocity(bead_ode.BeadSwimmers([sw(0, 0), sw(5e5, 0)], mu, tensor), T, 3, dt)[-1]
+    np.testing.assert_allclose(far, [alone, alone], rtol=1e-3)
+    ab = bead_ode.period_velocity(bead_ode.BeadSwimmers([sw(0, 0), sw(150, 0)], mu, tensor), T, 3, dt)[-1]
+    ba = bead_ode.period_velocity(bead_ode.BeadSwimmers([sw(150, 0), sw(0, 0)], mu, tensor), T, 3, dt)[-1]
+    np.testing.assert_allclose(ab, ba[::-1], rtol=1e-12)
