@@ -78,6 +78,18 @@ typedef struct {
   float fp16_scale;    /* power of two S for FP16_SHIFTED (0 = default 1) */
   int32_t use_graphs;  /* 1 = replay steps from captured HIP graphs */
   void* stream;        /* hipStream_t to enqueue on; NULL = own stream */
+  /* Device memory for the node fields (both population sets, the body-force
+   * density and the velocity), e.g. a tensor the caller allocated; NULL = the
+   * handle allocates them.  At least lbm_field_bytes() bytes, 256-byte
+   * aligned, on the handle's device.  The caller owns it, keeps it alive and
+   * untouched until lbm_destroy, and frees it afterwards; lbm_create
+   * overwrites it with the rest state.  The handle's other device memory
+   * stays its own: mesh tables, bead, tile, block-flag and reduction
+   * buffers (at most a few bytes per 128 nodes), and, made on first use, the
+   * staging of lbm_get_velocity into host memory, the sums of the time
+   * average and the adjoint's workspace. */
+  void* field_memory;
+  int64_t field_bytes; /* size of field_memory in bytes */
 } lbm_opts;
 
 typedef struct {
@@ -110,12 +122,15 @@ typedef struct lbm_handle lbm_handle;
  * tau (Eq. lbe; viscosity nu = (tau - 1/2)/3, Sec. 2.1).  Requires tau > 1/2,
  * every grid edge >= 16, at most 2^31 - 2^16 nodes (a batch: per box, and
  * fewer than 2^31 in all), forcing and opts valid.  opts may be NULL (FP32,
- * 3-point kernel, graphs on, own stream).  *out receives the handle.
- * Errors: LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE. */
+ * 3-point kernel, graphs on, own stream, fields allocated by the handle).
+ * *out receives the handle.  Errors: LBM_EINVAL (also: field_memory not
+ * 256-byte aligned or field_bytes below lbm_field_bytes), LBM_ENOMEM,
+ * LBM_EDEVICE. */
 int lbm_create(const lbm_grid* grid, double tau, int forcing, const lbm_opts* opts,
                lbm_handle** out);
 
-/* Release all device memory and the handle.  Accepts NULL. */
+/* Release the handle's own device memory and the handle (not caller field
+ * memory).  Accepts NULL. */
 int lbm_destroy(lbm_handle* h);
 
 /* Add one three-bead swimmer (Sec. 2.2, Fig. 1): beads[0..2] in order along
@@ -217,6 +232,14 @@ typedef struct {
  * in the order they were added.  Errors: as lbm_create. */
 int lbm_batch_create(const lbm_box_desc* boxes, int32_t nboxes, const lbm_opts* opts,
                      lbm_handle** out);
+
+/* Bytes of caller field memory (lbm_opts.field_memory) that a handle over
+ * these boxes with this storage (lbm_storage) needs: two population sets
+ * (19 values per node, 4 bytes each, 2 with FP16_SHIFTED) plus 3 float32 of
+ * body force and 3 of velocity per node, each part padded to the population
+ * blocks of 256 nodes.  Host-only; no device is touched.  Errors: LBM_EINVAL
+ * (boxes that lbm_batch_create would reject, unknown storage, NULL bytes). */
+int lbm_field_bytes(const lbm_box_desc* boxes, int32_t nboxes, int32_t storage, int64_t* bytes);
 /* Add a swimmer (as lbm_swimmer_add) to box `box`.  Swimmers must be added in
  * non-decreasing box order (LBM_EINVAL otherwise). */
 int lbm_batch_swimmer_add(lbm_handle* h, int32_t box, const lbm_bead_desc beads[3],

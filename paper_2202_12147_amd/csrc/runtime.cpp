@@ -581,9 +581,10 @@ const char* lbm_last_error(const lbm_handle* h) { return h ? h->err.c_str() : "n
 
 namespace {
 
-int create_boxes(const lbm_box_desc* boxes, int nboxes, const lbm_opts* opts, lbm_handle** out) {
-  if (!out || !boxes || nboxes < 1) return LBM_EINVAL;
-  *out = nullptr;
+// Box descriptors as lbm_batch_create accepts them; *nodes receives the
+// total node count.
+int check_boxes(const lbm_box_desc* boxes, int nboxes, int64_t* nodes) {
+  if (!boxes || nboxes < 1) return LBM_EINVAL;
   int64_t total = 0;
   for (int b = 0; b < nboxes; ++b) {
     const lbm_box_desc& d = boxes[b];
@@ -596,10 +597,43 @@ int create_boxes(const lbm_box_desc* boxes, int nboxes, const lbm_opts* opts, lb
     total += (int64_t)d.grid.nx * d.grid.ny * d.grid.nz;
   }
   if (total >= (int64_t)1 << 31) return LBM_EINVAL;
-  lbm_opts o{LBM_FP32_SHIFTED, 3, 1.0f, 1, nullptr};
+  *nodes = total;
+  return LBM_OK;
+}
+
+bool valid_storage(int storage) {
+  return storage == LBM_FP32_SHIFTED || storage == LBM_FP16_SHIFTED || storage == LBM_FP32_PLAIN;
+}
+
+// The node fields in one allocation: population sets 0 and 1, then the
+// body-force density and the velocity ([3][pstride] float32 each).  Every
+// part is a multiple of 256 bytes long (pstride is a multiple of the
+// 256-node population block), so each starts 256-byte aligned.
+struct FieldLayout {
+  size_t pop, vec, total;  // bytes of one population set, of F (or u), of all
+};
+
+FieldLayout field_layout(int64_t nodes, int storage) {
+  const int64_t pstride = (nodes + kPopBlock - 1) / kPopBlock * kPopBlock;
+  FieldLayout L;
+  L.pop = (size_t)(storage == LBM_FP16_SHIFTED ? 2 : 4) * kQ * (size_t)pstride;
+  L.vec = sizeof(float) * 3 * (size_t)pstride;
+  L.total = 2 * L.pop + 2 * L.vec;
+  return L;
+}
+
+int create_boxes(const lbm_box_desc* boxes, int nboxes, const lbm_opts* opts, lbm_handle** out) {
+  if (!out) return LBM_EINVAL;
+  *out = nullptr;
+  int64_t total = 0;
+  if (int rc = check_boxes(boxes, nboxes, &total)) return rc;
+  lbm_opts o{LBM_FP32_SHIFTED, 3, 1.0f, 1, nullptr, nullptr, 0};
   if (opts) o = *opts;
-  if (o.storage != LBM_FP32_SHIFTED && o.storage != LBM_FP16_SHIFTED && o.storage != LBM_FP32_PLAIN)
-    return LBM_EINVAL;
+  if (!valid_storage(o.storage)) return LBM_EINVAL;
+  if (o.field_memory) {
+    if (((uintptr_t)o.field_memory & 255) != 0) return LBM_EINVAL;
+    if (o.field_bytes < 0 || (uint64_t)o.field_bytes < field_layout(total, o.storage).total) return LBM_EINVAL;
+  }
   if (o.delta_width < 2 || o.delta_width > 4) return LBM_EINVAL;
   if (o.fp16_scale == 0.0f) o.fp16_scale = 1.0f;
   {
@@ -687,10 +721,20 @@ int create_boxes(const lbm_box_desc* boxes, int nboxes, const lbm_opts* opts, lb
   }
 
   const size_t eb = element_bytes(h);
-  h->pop[0] = h->alloc<char>(eb * kQ * h->pstride, rc);
-  h->pop[1] = h->alloc<char>(eb * kQ * h->pstride, rc);
-  h->F = h->alloc<float>(3 * h->pstride, rc);
-  h->u = h->alloc<float>(3 * h->pstride, rc);
+  if (o.field_memory) {
+    // the caller's memory, laid out as field_layout says; never freed here
+    const FieldLayout L = field_layout(h->nodes, h->storage);
+    char* base = static_cast<char*>(o.field_memory);
+    h->pop[0] = base;
+    h->pop[1] = base + L.pop;
+    h->F = reinterpret_cast<float*>(base + 2 * L.pop);
+    h->u = reinterpret_cast<float*>(base + 2 * L.pop + L.vec);
+  } else {
+    h->pop[0] = h->alloc<char>(eb * kQ * h->pstride, rc);
+    h->pop[1] = h->alloc<char>(eb * kQ * h->pstride, rc);
+    h->F = h->alloc<float>(3 * h->pstride, rc);
+    h->u = h->alloc<float>(3 * h->pstride, rc);
+  }
   h->stamp = h->alloc<int>(h->ntiles, rc);
   h->d_boxes = h->alloc<Box>(nboxes, rc);
   h->d_step = h->alloc<int64_t>(1, rc);
@@ -767,6 +811,14 @@ int lbm_create(const lbm_grid* grid, double tau, int forcing, const lbm_opts* op
 
 int lbm_batch_create(const lbm_box_desc* boxes, int32_t nboxes, const lbm_opts* opts, lbm_handle** out) {
   return create_boxes(boxes, nboxes, opts, out);
+}
+
+int lbm_field_bytes(const lbm_box_desc* boxes, int32_t nboxes, int32_t storage, int64_t* bytes) {
+  if (!bytes || !valid_storage(storage)) return LBM_EINVAL;
+  int64_t nodes = 0;
+  if (int rc = check_boxes(boxes, nboxes, &nodes)) return rc;
+  *bytes = (int64_t)field_layout(nodes, storage).total;
+  return LBM_OK;
 }
 
 int32_t lbm_n_boxes(const lbm_handle* h) { return h ? (int32_t)h->boxes.size() : -1; }

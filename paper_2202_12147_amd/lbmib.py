@@ -31,7 +31,7 @@ SYMBOLS = [
     "lbm_probe_copy_bandwidth", "lbm_set_stream_collide_launch",
     "lbm_batch_create", "lbm_batch_swimmer_add", "lbm_n_boxes", "lbm_batch_get_velocity",
     "lbm_batch_get_conserved", "lbm_batch_get_conserved_noalloc", "lbm_autotune",
-    "lbm_swimmer_set_params", "lbm_adjoint",
+    "lbm_swimmer_set_params", "lbm_adjoint", "lbm_field_bytes",
     "lbm_strerror", "lbm_last_error",
 ]
 
@@ -48,7 +48,8 @@ class Grid(C.Structure):
 
 class Opts(C.Structure):
     _fields_ = [("storage", C.c_int32), ("delta_width", C.c_int32), ("fp16_scale", C.c_float),
-                ("use_graphs", C.c_int32), ("stream", C.c_void_p)]
+                ("use_graphs", C.c_int32), ("stream", C.c_void_p), ("field_memory", C.c_void_p),
+                ("field_bytes", C.c_int64)]
 
 
 class BoxDesc(C.Structure):
@@ -142,6 +143,7 @@ def bind(lib):
         "lbm_autotune": (C.c_int, [vp, i32, C.c_char_p, C.c_char_p, i32]),
         "lbm_swimmer_set_params": (C.c_int, [vp, i32, C.c_double, C.c_double, C.c_double, C.c_double]),
         "lbm_adjoint": (C.c_int, [vp, C.POINTER(AdjointDesc), C.POINTER(C.c_double), dp]),
+        "lbm_field_bytes": (C.c_int, [C.POINTER(BoxDesc), i32, i32, C.POINTER(i64)]),
         "lbm_strerror": (C.c_char_p, [C.c_int]),
         "lbm_last_error": (C.c_char_p, [vp]),
     }
@@ -186,14 +188,57 @@ def _swimmer_descs(sw):
     return beads, springs, act
 
 
+def field_bytes(boxes, storage=FP32_SHIFTED):
+    """Bytes of caller field memory a handle over ``boxes`` (list of (shape,
+    tau, forcing)) needs (lbm_field_bytes; host only)."""
+    lib = load_library()
+    arr = _box_array(boxes)
+    out = C.c_int64()
+    rc = lib.lbm_field_bytes(arr, len(boxes), int(storage), C.byref(out))
+    if rc:
+        raise LbmError(rc, lib.lbm_strerror(rc).decode())
+    return out.value
+
+
+def _box_array(boxes):
+    arr = (BoxDesc * len(boxes))()
+    for i, (shape, tau, forcing) in enumerate(boxes):
+        arr[i].grid = Grid(*[int(v) for v in shape])
+        arr[i].tau = float(tau)
+        arr[i].forcing = int(forcing)
+    return arr
+
+
+def _field_memory(boxes, storage, field_memory):
+    """(tensor or None, pointer, bytes) for Opts: None lets the library
+    allocate; "torch" allocates a uint8 tensor of the needed size on the
+    current device; a contiguous device tensor is used as given."""
+    if field_memory is None:
+        return None, None, 0
+    import torch
+    need = field_bytes(boxes, storage)
+    if isinstance(field_memory, str):
+        if field_memory != "torch":
+            raise ValueError("field_memory: None, 'torch' or a device tensor")
+        t = torch.empty(need, dtype=torch.uint8, device=torch.device("cuda", torch.cuda.current_device()))
+    else:
+        t = field_memory
+        if not (t.is_cuda and t.is_contiguous()):
+            raise ValueError("field_memory must be a contiguous device tensor")
+    return t, t.data_ptr(), t.numel() * t.element_size()
+
+
 class Lattice:
     """One periodic D3Q19 box with swimmers, stepped by the HIP library.
 
     ``stream``: a ``torch.cuda.Stream`` (or raw hipStream_t int) to enqueue on;
-    None lets the library create its own."""
+    None lets the library create its own.  ``field_memory``: None (the
+    library allocates the node fields), "torch" (a tensor allocated here) or
+    a contiguous device tensor of at least ``field_bytes`` bytes; the handle
+    keeps a reference for its lifetime (``self.field_tensor``)."""
 
     def __init__(self, shape, tau, forcing=GUO, storage=FP32_SHIFTED, width=3, fp16_scale=1.0,
-                 use_graphs=True, stream=None):
+                 use_graphs=True, stream=None, field_memory=None):
         self.lib = load_library()
         self.shape = tuple(int(s) for s in shape)
         self.storage = storage
@@ -201,8 +246,9 @@ class Lattice:
         if stream is not None:
             raw = getattr(stream, "cuda_stream", stream)
             raw = int(raw) or None
+        self.field_tensor, fptr, fbytes = _field_memory([(self.shape, tau, forcing)], storage, field_memory)
         g = Grid(*self.shape)
-        o = Opts(int(storage), int(width), float(fp16_scale), int(bool(use_graphs)), raw)
+        o = Opts(int(storage), int(width), float(fp16_scale), int(bool(use_graphs)), raw, fptr, fbytes)
         h = C.c_void_p()
         rc = self.lib.lbm_create(C.byref(g), float(tau), int(forcing), C.byref(o), C.byref(h))
         if rc:
@@ -216,8 +262,9 @@ class Lattice:
 
     def close(self):
         if getattr(self, "h", None):
-            self.lib.lbm_destroy(self.h)
+            self.lib.lbm_destroy(self.h)  # waits for the handle's stream
             self.h = None
+        self.field_tensor = None
 
     def __del__(self):
         try:
@@ -421,7 +468,7 @@ class Batch(Lattice):
     step over all boxes).  ``boxes``: list of (shape, tau, forcing)."""
 
     def __init__(self, boxes, storage=FP32_SHIFTED, width=3, fp16_scale=1.0, use_graphs=True,
-                 stream=None):
+                 stream=None, field_memory=None):
         self.lib = load_library()
         self.shapes = [tuple(int(v) for v in b[0]) for b in boxes]
         self.shape = self.shapes[0]
@@ -429,12 +476,9 @@ class Batch(Lattice):
         raw = None
         if stream is not None:
             raw = int(getattr(stream, "cuda_stream", stream)) or None
-        arr = (BoxDesc * len(boxes))()
-        for i, (shape, tau, forcing) in enumerate(boxes):
-            arr[i].grid = Grid(*[int(v) for v in shape])
-            arr[i].tau = float(tau)
-            arr[i].forcing = int(forcing)
-        o = Opts(int(storage), int(width), float(fp16_scale), int(bool(use_graphs)), raw)
+        arr = _box_array(boxes)
+        self.field_tensor, fptr, fbytes = _field_memory(boxes, storage, field_memory)
+        o = Opts(int(storage), int(width), float(fp16_scale), int(bool(use_graphs)), raw, fptr, fbytes)
         h = C.c_void_p()
         rc = self.lib.lbm_batch_create(arr, len(boxes), C.byref(o), C.byref(h))
         if rc:
@@ -476,22 +520,23 @@ class Batch(Lattice):
         return out
 
 
-def batch_from_ensemble(ens, storage=FP32_SHIFTED, use_graphs=True, stream=None):
+def batch_from_ensemble(ens, storage=FP32_SHIFTED, use_graphs=True, stream=None, field_memory=None):
     """Build a Batch from a ``workloads.ensemble`` dict (boxes share the
     kernel width of the first box)."""
     boxes = ens["boxes"]
     b = Batch([(bx["shape"], bx["tau"], bx["forcing"]) for bx in boxes], storage,
-              boxes[0]["width"], use_graphs=use_graphs, stream=stream)
+              boxes[0]["width"], use_graphs=use_graphs, stream=stream, field_memory=field_memory)
     for i, bx in enumerate(boxes):
         for sw in bx["swimmers"]:
             b.add_swimmer(sw, box=i)
     return b
 
 
-def from_workload(case, storage=FP32_SHIFTED, fp16_scale=1.0, use_graphs=True, stream=None):
+def from_workload(case, storage=FP32_SHIFTED, fp16_scale=1.0, use_graphs=True, stream=None,
+                  field_memory=None):
     """Build a Lattice with the swimmers of a ``workloads`` case dict."""
     lat = Lattice(case["shape"], case["tau"], case["forcing"], storage, case["width"], fp16_scale,
-                  use_graphs, stream)
+                  use_graphs, stream, field_memory)
     for sw in case.get("swimmers", []):
         lat.add_swimmer(sw)
     return lat

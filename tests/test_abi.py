@@ -64,6 +64,38 @@ def test_invalid_arguments_rejected():
     assert lib.lbm_destroy(None) == 0
 
 
+def test_field_bytes_and_caller_memory_checks():
+    """lbm_field_bytes: two population sets (19 x 4 bytes per node, 19 x 2
+    with FP16 storage) plus 3 + 3 float32 of force and velocity per node, the
+    node count padded to whole 256-node population blocks (a batch: the sum
+    of its boxes, padded once).  Caller memory that is misaligned or too small
+    is refused before any device call."""
+    lib = lbmib.load_library()
+    out = C.c_int64()
+    one = (lbmib.BoxDesc * 1)(lbmib.BoxDesc(lbmib.Grid(128, 128, 128), 0.8, 0))
+    assert lib.lbm_field_bytes(one, 1, 0, C.byref(out)) == 0
+    assert out.value == 128 ** 3 * (2 * 19 * 4 + 24)
+    assert lbmib.field_bytes([((128, 128, 128), 0.8, 0)], lbmib.FP16_SHIFTED) == 128 ** 3 * (2 * 19 * 2 + 24)
+    ragged = [((100, 20, 17), 1.0, 0), ((16, 16, 17), 0.7, 1)]
+    padded = -(-(100 * 20 * 17 + 16 * 16 * 17) // 256) * 256
+    assert lbmib.field_bytes(ragged) == padded * (2 * 19 * 4 + 24)
+    assert lbmib.field_bytes(ragged, lbmib.FP32_PLAIN) == padded * (2 * 19 * 4 + 24)
+    assert lib.lbm_field_bytes(one, 1, 9, C.byref(out)) == -1  # storage
+    assert lib.lbm_field_bytes(one, 1, 0, None) == -1
+    assert lib.lbm_field_bytes(one, 0, 0, C.byref(out)) == -1
+    bad = (lbmib.BoxDesc * 1)(lbmib.BoxDesc(lbmib.Grid(8, 128, 128), 0.8, 0))
+    assert lib.lbm_field_bytes(bad, 1, 0, C.byref(out)) == -1
+    h = C.c_void_p()
+    g = lbmib.Grid(128, 128, 128)
+    need = 128 ** 3 * (2 * 19 * 4 + 24)
+    o = lbmib.Opts(0, 3, 1.0, 1, None, 0x10000 + 8, need)  # not 256-byte aligned
+    assert lib.lbm_create(C.byref(g), 1.0, 0, C.byref(o), C.byref(h)) == -1
+    o = lbmib.Opts(0, 3, 1.0, 1, None, 0x10000, need - 1)  # too small
+    assert lib.lbm_create(C.byref(g), 1.0, 0, C.byref(o), C.byref(h)) == -1
+    assert lib.lbm_batch_create(one, 1, C.byref(o), C.byref(h)) == -1
+    assert h.value is None
+
+
 def test_binding_refuses_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(lbmib, "LIB_PATH", str(tmp_path / "missing.so"))
     monkeypatch.setattr(lbmib, "_lib", None)
