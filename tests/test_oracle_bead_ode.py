@@ -137,3 +137,34 @@ def test_pair_limits_and_symmetry(tensor):
     ab = bead_ode.period_velocity(bead_ode.BeadSwimmers([sw(0, 0), sw(150, 0)], mu, tensor), T, 3, dt)[-1]
     ba = bead_ode.period_velocity(bead_ode.BeadSwimmers([sw(150, 0), sw(0, 0)], mu, tensor), T, 3, dt)[-1]
     np.testing.assert_allclose(ab, ba[::-1], rtol=1e-12)
+
+
+@pytest.mark.parametrize("tensor", ["oseen", "rotne_prager"])
+def test_delayed_interaction_closed_form(tensor):
+    """Eq. fit-eq: the flow at bead i comes from the other beads' forces and
+    positions a time tau_d earlier.  A swimmer with no springs, driven on
+    bead 1 only (f1 = A sin(w t), f2 = -f1, f3 = 0), leaves bead 3 force-free,
+    so bead 3 moves only with the delayed flow of beads 1 and 2 (whose tiny
+    displacements are negligible at A = 1e-6).  Along the axis its
+    displacement from 0 to t1 > tau_d is
+        (T_xx(r31) - T_xx(r32)) A (1 - cos(w (t1 - tau_d))) / w,
+    T_xx(r) = 2 (1 - 2a^2/(3r^2)) / (8 pi mu r) (a = 0 for Oseen): nothing
+    before tau_d, since the delayed forces before t = 0 are the initial ones,
+    which vanish."""
+    mu, T, a, L, A, tau, t1, dt = 1.0 / 6.0, 400.0, 1.0, 20.0, 1e-6, 100.0, 250.0, 0.5
+    sw = wl.swimmer((0.0, 0.0, 0.0), L, radius=a, k=0.0, A=A, B=0.0, T=T)
+    m = bead_ode.BeadSwimmers([sw], mu=mu, tensor=tensor, delay=tau)
+    x3 = m.R[2, 0]
+    m.run(int(round(t1 / dt)), dt)
+    c = (lambda r: 2.0 * a * a / (3.0 * r * r)) if tensor == "rotne_prager" else (lambda r: 0.0)
+    txx = lambda r: 2.0 * (1.0 - c(r)) / (8.0 * math.pi * mu * r)
+    w = 2.0 * math.pi / T
+    want = (txx(2 * L) - txx(L)) * A * (1.0 - math.cos(w * (t1 - tau))) / w
+    got = m.R[2, 0] - x3
+    print(tensor, "displacement", got, "closed form", want)
+    assert abs(got - want) <= 2e-4 * abs(want)
+    # the same run without the delay follows the undelayed phase instead
+    m0 = bead_ode.BeadSwimmers([sw], mu=mu, tensor=tensor)
+    m0.run(int(round(t1 / dt)), dt)
+    want0 = (txx(2 * L) - txx(L)) * A * (1.0 - math.cos(w * t1)) / w
+    assert abs((m0.R[2, 0] - x3) - want0) <= 2e-4 * abs(want0)
