@@ -161,3 +161,26 @@ def period_velocity(model, period, periods, dt=1.0):
         X.append(model.run(steps, dt)[-1])
     X = np.array(X)
     return (X[1:, :, 0] - X[:-1, :, 0]) / period
+
+
+def relative_changes(pair, single, mu, tensor="rotne_prager", delay=0.0, period=2e4, periods=4, dt=4.0):
+    """v_Delta = (v - v_ref) / v_ref (Eq. inc) of each swimmer of `pair`
+    against the lone swimmer `single`, both over the last of `periods`
+    periods, in the same model."""
+    v_ref = period_velocity(BeadSwimmers(single, mu, tensor, delay), period, periods, dt)[-1, 0]
+    v = period_velocity(BeadSwimmers(pair, mu, tensor, delay), period, periods, dt)[-1]
+    return v_ref, (v - v_ref) / v_ref
+
+
+if __name__ == "__main__":
+    # the paper-box runs' swimmers (Sec. 3) in the point-bead model, mu = 1/6
+    from paper_2202_12147_amd import workloads as wl
+
+    single = wl.paper_run()["swimmers"]
+    for arrangement, d in (("collinear", 144.0), ("side", 72.0)):
+        pair = wl.paper_run(arrangement, d)["swimmers"]
+        for tensor in ("oseen", "rotne_prager"):
+            for delay in ((0.0, 250.0, 500.0, 1000.0) if arrangement == "collinear" else (0.0,)):
+                v_ref, vd = relative_changes(pair, single, 1.0 / 6.0, tensor, delay)
+                print(f"{arrangement:9s} d={d:5.0f} {tensor:12s} delay {delay:6.0f}: v_ref {v_ref:.4e}, "
+                      f"v_Delta {' '.join(f'{x:+.4f}' for x in vd)}", flush=True)
