@@ -473,6 +473,10 @@ __global__ __launch_bounds__(BS) void k_stream_collide_claimed(Dev d, int remap,
   // g + 2G, ... (round robin), or, with `remap`, one contiguous range per
   // group.  The claim of the next block is issued before the current block's
   // work, which hides its latency; two claim slots need one barrier per block.
+  // Odd steps walk each group's blocks in reverse, so a step starts on the
+  // blocks the previous one wrote last, the likeliest to be still in the
+  // last-level cache (128^3 FP32 step 58.0 against 58.7 us; the full-grid
+  // launch gains nothing from the same reversal, 50.8 against 49.9 us).
   (void)resident;
   const int64_t n = *d.step + d.sub;
   const int64_t pn = n - 1;  // the step whose bead statistics marked the near blocks
@@ -491,7 +495,8 @@ __global__ __launch_bounds__(BS) void k_stream_collide_claimed(Dev d, int remap,
     if (j >= per) break;
     // slot (i + 1) & 1 was last read in iteration i - 1, before its barrier
     if (threadIdx.x == 0) next[(i + 1) & 1] = atomicAdd(ctr, 1);
-    const int blk = remap ? g * per + j : g + G * j;
+    const int jj = (n & 1) ? per - 1 - j : j;
+    const int blk = remap ? g * per + jj : g + G * jj;
     if (blk < nblocks && d.near[pf * d.nsc + blk] != (int)pn) sc_block<ST, BS, false, NTLD>(d, blk, n, true, avg);
     __syncthreads();
   }
