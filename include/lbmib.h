@@ -246,6 +246,9 @@ int lbm_batch_swimmer_add(lbm_handle* h, int32_t box, const lbm_bead_desc beads[
                           const lbm_spring_desc springs[2], const lbm_actuation_desc* act,
                           int32_t* id);
 int32_t lbm_n_boxes(const lbm_handle* h);
+/* Advance every box of a batch n steps: the same call as lbm_step (which
+ * accepts batch handles too), under the batch's name. */
+int lbm_batch_step(lbm_handle* h, int64_t n);
 /* Velocity (layout as lbm_get_velocity) of one box of the batch. */
 int lbm_batch_get_velocity(lbm_handle* h, int32_t box, float* dst, int on_device);
 /* Conserved sums (as lbm_get_conserved) of one box; box = -1 sums all boxes. */

@@ -997,6 +997,8 @@ int lbm_step(lbm_handle* h, int64_t n) {
   return LBM_OK;
 }
 
+int lbm_batch_step(lbm_handle* h, int64_t n) { return lbm_step(h, n); }
+
 int lbm_sync(lbm_handle* h) {
   if (!h) return LBM_EINVAL;
   int rc = h->hip(hipStreamSynchronize(h->stream), "hipStreamSynchronize");

@@ -29,7 +29,7 @@ SYMBOLS = [
     "lbm_average_begin", "lbm_get_average_velocity",
     "lbm_save", "lbm_load", "lbm_set_kernel_timing", "lbm_kernel_time", "lbm_bytes_per_step",
     "lbm_probe_copy_bandwidth", "lbm_set_stream_collide_launch",
-    "lbm_batch_create", "lbm_batch_swimmer_add", "lbm_n_boxes", "lbm_batch_get_velocity",
+    "lbm_batch_create", "lbm_batch_swimmer_add", "lbm_n_boxes", "lbm_batch_step", "lbm_batch_get_velocity",
     "lbm_batch_get_conserved", "lbm_batch_get_conserved_noalloc", "lbm_autotune",
     "lbm_swimmer_set_params", "lbm_adjoint", "lbm_field_bytes",
     "lbm_strerror", "lbm_last_error",
@@ -137,6 +137,7 @@ def bind(lib):
         "lbm_batch_swimmer_add": (C.c_int, [vp, i32, C.POINTER(BeadDesc), C.POINTER(SpringDesc),
                                             C.POINTER(ActuationDesc), C.POINTER(i32)]),
         "lbm_n_boxes": (i32, [vp]),
+        "lbm_batch_step": (C.c_int, [vp, i64]),
         "lbm_batch_get_velocity": (C.c_int, [vp, i32, fp, C.c_int]),
         "lbm_batch_get_conserved": (C.c_int, [vp, i32, dp]),
         "lbm_batch_get_conserved_noalloc": (C.c_int, [vp, i32, i32, dp]),
@@ -492,6 +493,9 @@ class Batch(Lattice):
     @property
     def n_boxes(self):
         return self.lib.lbm_n_boxes(self.h)
+
+    def step(self, n=1):
+        self._check(self.lib.lbm_batch_step(self.h, int(n)))
 
     def add_swimmer(self, sw, box=0):
         beads, springs, act = _swimmer_descs(sw)
