@@ -27,10 +27,14 @@ PEAK_HBM_GBS = 8000.0
 # remapped); FP16 (static persistent walk) at two of 256 nodes; the batch
 # and the 1024x256x256 box non-persistent with the XCD remap (batch 724.7
 # against 729.5 us in block order, 760-940 us persistent; box 1.842 ms
-# against 1.849 ms in block order and 1.869 ms at block 256)
+# against 1.849 ms in block order and 1.869 ms at block 256).  The batch
+# section itself runs the launch tuner (lbmib.tune_launch) and times the
+# shape it picks (block order, 707.6 us against 731.5 us remapped, in the
+# tuner's first run); BATCH_LAUNCH is that shape, which the parity test of
+# the full ensemble uses.  The paper-box section tunes too.
 MAIN_LAUNCH = (512, False, 1)
 FP16_LAUNCH = (256, False, 2)
-BATCH_LAUNCH = (512, True, 0)
+BATCH_LAUNCH = (512, False, 0)
 BOX_LAUNCH = (512, True, 0)
 KERNEL_LAUNCH = (256, False, -1)  # serial order: full-grid launch for the roofline
 PMC_PROFILE = os.path.join(ROOT, "profiles", "stream_collide_128cubed_pmc.txt")
@@ -180,12 +184,16 @@ def seeds_section(lbmib, wl, seeds=(1, 2), steps=4000, warmup=200):
 
 def batch_section(lbmib, wl, steps=5000, warmup=200, seed=0):
     """The 64-box ensemble (edges from {48,64,80,96} per axis, one swimmer
-    each) advanced together at the launch shape measured best for it by
-    explicit sweeps (BATCH_LAUNCH), `steps` timed steps; batch MLUPS = total
-    nodes x steps / time."""
+    each) advanced together at the launch shape the tuner picks for it
+    (lbmib.tune_launch: every candidate timed on a scratch batch of the same
+    ensemble, 200 steps, best of two passes), `steps` timed steps; batch
+    MLUPS = total nodes x steps / time."""
     ens = wl.ensemble(seed=seed)
+    t0 = time.perf_counter()
+    best, table = lbmib.tune_launch(lambda: lbmib.batch_from_ensemble(ens))
+    tune_s = time.perf_counter() - t0
     batch = lbmib.batch_from_ensemble(ens)
-    batch.set_stream_collide_launch(*BATCH_LAUNCH)
+    batch.set_stream_collide_launch(*best)
     batch.step(warmup)
     batch.sync()
     t0 = time.perf_counter()
@@ -195,7 +203,9 @@ def batch_section(lbmib, wl, steps=5000, warmup=200, seed=0):
     return {"value": round(batch.N * steps / dt / 1e6, 1), "unit": "MLUPS", "steps": steps,
             "ms_per_step": round(dt / steps * 1e3, 4), "boxes": len(ens["boxes"]), "nodes": batch.N,
             "markers": batch.n_markers, "seed": seed,
-            "launch": {"block": BATCH_LAUNCH[0], "xcd_remap": int(BATCH_LAUNCH[1]), "resident": BATCH_LAUNCH[2]}}
+            "launch": {"block": best[0], "xcd_remap": int(best[1]), "resident": best[2]},
+            "tuner": {"seconds": round(tune_s, 1),
+                      "us_per_step": {f"{b}/{int(r)}/{p}": round(v, 1) for (b, r, p), v in table.items()}}}
 
 
 def adjoint_section(lbmib, wl, use_graphs=True):
@@ -229,11 +239,16 @@ def adjoint_section(lbmib, wl, use_graphs=True):
 
 def paper_box_section(lbmib, wl, steps=500, warmup=50):
     """Throughput on the paper's 1024x256x256 box (67.1 M nodes, 10.2 GB of
-    FP32 populations per step) with one radius-5 swimmer."""
+    FP32 populations per step) with one radius-5 swimmer, at the launch shape
+    the tuner picks on a scratch handle of the same box (60 steps per
+    candidate, best of two passes)."""
     case = wl.paper_box()
     nodes = case["shape"][0] * case["shape"][1] * case["shape"][2]
+    t0 = time.perf_counter()
+    best, table = lbmib.tune_launch(lambda: lbmib.from_workload(case), steps=60, warmup=20)
+    tune_s = time.perf_counter() - t0
     lat = lbmib.from_workload(case)
-    lat.set_stream_collide_launch(*BOX_LAUNCH)
+    lat.set_stream_collide_launch(*best)
     lat.step(warmup)
     lat.sync()
     t0 = time.perf_counter()
@@ -243,7 +258,10 @@ def paper_box_section(lbmib, wl, steps=500, warmup=50):
     return {"workload": case["name"], "nodes": nodes, "markers": lat.n_markers, "steps": steps,
             "value": round(nodes * steps / dt / 1e6, 1), "unit": "MLUPS",
             "ms_per_step": round(dt / steps * 1e3, 4),
-            "step_gbs": round(lat.bytes_per_step / (dt / steps) / 1e9, 1)}
+            "step_gbs": round(lat.bytes_per_step / (dt / steps) / 1e9, 1),
+            "launch": {"block": best[0], "xcd_remap": int(best[1]), "resident": best[2]},
+            "tuner": {"seconds": round(tune_s, 1),
+                      "us_per_step": {f"{b}/{int(r)}/{p}": round(v, 1) for (b, r, p), v in table.items()}}}
 
 
 def kernels_section(lbmib):

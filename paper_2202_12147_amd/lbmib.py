@@ -7,6 +7,7 @@ binding refuses to run without the compiled library: there is no fallback.
 import ctypes as C
 import math
 import os
+import time
 
 import numpy as np
 
@@ -446,6 +447,43 @@ class Lattice:
         grad = np.zeros(4)
         self._check(self.lib.lbm_adjoint(self.h, C.byref(desc), C.byref(J), _ptr(grad)))
         return J.value, grad
+
+
+# Stream-collide launch shapes (block, xcd_remap, resident) the tuner tries:
+# workgroups of 128 / 256 / 512 nodes, block order round robin over the XCDs
+# or one contiguous range per XCD, one workgroup per block or 1-4 persistent
+# workgroups per CU.
+LAUNCH_CANDIDATES = ((512, True, 0), (512, False, 0), (256, True, 0), (256, False, 0), (128, True, 0),
+                     (512, False, 1), (512, True, 1), (512, False, 2), (256, False, 2), (256, False, 4))
+
+
+def tune_launch(make, candidates=LAUNCH_CANDIDATES, steps=200, warmup=50, rounds=2):
+    """Pick the fastest stream-collide launch shape for a workload.
+
+    ``make()`` builds a scratch handle over the same boxes and swimmers as
+    the handle to be tuned (e.g. ``lambda: batch_from_ensemble(ens)``), so
+    the caller's state is never touched.  Each candidate runs ``warmup``
+    steps, then ``steps`` timed steps (host clock around synchronised
+    stepping, graph replays as in use); ``rounds`` passes alternate the
+    candidate order and each candidate keeps its best pass.  The scratch
+    handle is destroyed before returning.  Returns (best shape,
+    {shape: microseconds per step})."""
+    lat = make()
+    try:
+        res = {}
+        for r in range(rounds):
+            for c in (candidates if r % 2 == 0 else candidates[::-1]):
+                lat.set_stream_collide_launch(*c)
+                lat.step(warmup)
+                lat.sync()
+                t0 = time.perf_counter()
+                lat.step(steps)
+                lat.sync()
+                us = (time.perf_counter() - t0) / steps * 1e6
+                res[c] = min(res.get(c, math.inf), us)
+        return min(res, key=res.get), res
+    finally:
+        lat.close()
 
 
 def fp16_scale_for(max_abs_dev, headroom=16.0):

@@ -134,6 +134,24 @@ def test_tuner_is_disabled_and_changes_nothing():
     assert np.array_equal(a.markers(), b.markers())
 
 
+def test_launch_tuner_on_a_scratch_batch():
+    # lbmib.tune_launch times every candidate shape on a scratch batch of the
+    # same ensemble and picks the fastest; the picked shape then runs the
+    # caller's batch bit for bit like the default shape
+    ens = wl.ensemble(seed=5, nboxes=3)
+    print("tuner: ensemble seed 5, 3 boxes", flush=True)
+    best, table = lbmib.tune_launch(lambda: lbmib.batch_from_ensemble(ens), steps=40, warmup=10)
+    print("tuned", best, {k: round(v, 1) for k, v in table.items()}, flush=True)
+    assert set(table) == set(lbmib.LAUNCH_CANDIDATES) and best == min(table, key=table.get)
+    a = lbmib.batch_from_ensemble(ens)
+    b = lbmib.batch_from_ensemble(ens)
+    a.set_stream_collide_launch(*best)
+    a.step(30)
+    b.step(30)
+    assert np.array_equal(a.markers(), b.markers())
+    assert np.array_equal(a.populations(), b.populations())
+
+
 def test_batch_with_an_empty_box_equals_single_boxes():
     # the middle box holds no swimmer (a gap in the bead -> box tables) and
     # runs Shan-Chen forcing; every box equals its own single-box run bit for bit

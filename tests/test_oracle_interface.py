@@ -114,3 +114,21 @@ def _invalid_calls(lib):
 def test_invalid_calls_fail_alike(olib):
     hip = lbmib.load_library()
     assert _invalid_calls(olib) == _invalid_calls(hip)
+
+
+def test_launch_tuner_logic_on_the_oracle_interface(olib):
+    """lbmib.tune_launch over the oracle's interface (which accepts launch
+    shapes and ignores them): every candidate is timed in both passes, the
+    best is the fastest of the table, and the scratch handle is destroyed;
+    the caller's handle is never built or stepped by the tuner."""
+    made = []
+
+    def make():
+        made.append(interface_lattice(olib, wl.small_case()))
+        return made[-1]
+
+    cands = ((512, True, 0), (256, False, 2), (128, True, 0))
+    best, table = lbmib.tune_launch(make, cands, steps=2, warmup=1)
+    assert len(made) == 1 and made[0].h is None  # closed
+    assert set(table) == set(cands) and all(v > 0 for v in table.values())
+    assert best == min(table, key=table.get)
