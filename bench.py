@@ -299,7 +299,8 @@ def kernels_section(lbmib):
     return out
 
 
-def paper_length_section(lbmib, wl, periods, out_dir=None, arrangement=None, distance=None, v_ref=None):
+def paper_length_section(lbmib, wl, periods, out_dir=None, arrangement=None, distance=None, v_ref=None,
+                         tau=1.0):
     """The paper's runs over `periods` actuation periods of 2e4 steps on the
     1024x256x256 box (workloads.paper_run): one swimmer, or a pair one behind
     the other / side by side at a given distance of their middle beads.  Per
@@ -310,7 +311,7 @@ def paper_length_section(lbmib, wl, periods, out_dir=None, arrangement=None, dis
     the last period (Eq. inc); and the velocity field averaged over the last
     period (Figs. 3, 6, 9), saved downsampled when out_dir is set."""
     import numpy as np
-    case = wl.paper_run(arrangement, distance)
+    case = wl.paper_run(arrangement, distance, tau)
     sw = case["swimmers"][0]
     T = int(case["period"])
     nu = (case["tau"] - 0.5) / 3.0
@@ -383,6 +384,8 @@ def main():
                     help="with --paper-pair: distance of the middle beads (lattice units)")
     ap.add_argument("--paper-vref", type=float, default=None,
                     help="with --paper-pair: a single swimmer's velocity, for the relative changes")
+    ap.add_argument("--paper-tau", type=float, default=1.0,
+                    help="with --paper-length: relaxation time (viscosity sweeps; the paper's run is 1)")
     ap.add_argument("--main-only", action="store_true",
                     help="skip the fp16, batch, adjoint and paper-box sections (counter runs)")
     args = ap.parse_args()
@@ -408,7 +411,7 @@ def main():
     if args.paper_length:
         print(json.dumps({"paper_length": paper_length_section(
             lbmib, wl, args.paper_length, args.paper_out, args.paper_pair,
-            args.paper_distance if args.paper_pair else None, args.paper_vref)}), flush=True)
+            args.paper_distance if args.paper_pair else None, args.paper_vref, args.paper_tau)}), flush=True)
         return
     case = wl.single_128(seed=0)
     nodes = case["shape"][0] * case["shape"][1] * case["shape"][2]

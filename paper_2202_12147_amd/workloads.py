@@ -149,9 +149,10 @@ def paper_moduli_case(adjoint=False):
                                   **PAPER_MODULI)])
 
 
-def paper_run(arrangement=None, distance=None):
+def paper_run(arrangement=None, distance=None, tau=1.0):
     """The paper's single-swimmer run (Sec. 3): 1024x256x256 fully periodic
-    box, tau 1 (mu = 1/6), Shan-Chen forcing as in the paper, radius-5 beads
+    box, tau 1 (mu = 1/6; other tau for the paper's viscosity sweeps, mu =
+    (tau - 1/2)/3 at rho0 = 1), Shan-Chen forcing as in the paper, radius-5 beads
     with the paper's moduli (refined twice, as in paper_moduli_case), rest
     length 36, k = 0.02, A = B = 5e-3 (the printed A = 1e-1 contradicts the
     bead Reynolds number the paper reports), T = 2e4, alpha = pi/2, 3-point
@@ -174,7 +175,9 @@ def paper_run(arrangement=None, distance=None):
         else:
             raise ValueError(arrangement)
         swimmers, name = [one(m) for m in mids], f"paper pair run 1024x256x256, {arrangement}, d = {distance:g}"
-    return dict(name=name, shape=(1024, 256, 256), tau=1.0, forcing=SHAN_CHEN, width=3, steps=12 * 20000,
+    if tau != 1.0:
+        name += f", tau = {tau:g}"
+    return dict(name=name, shape=(1024, 256, 256), tau=float(tau), forcing=SHAN_CHEN, width=3, steps=12 * 20000,
                 period=20000, swimmers=swimmers)
 
 
