@@ -33,6 +33,11 @@ PEAK_HBM_GBS = 8000.0
 # tuner's first run); BATCH_LAUNCH is that shape, which the parity test of
 # the full ensemble uses.  The paper-box section tunes too.
 MAIN_LAUNCH = (512, False, 1)
+# The 128^3 workload's populations: FP32 deviations in one set updated in
+# place (LBM_FP32_INPLACE; 159 MB instead of two sets of 319 MB, which the
+# 256 MB last-level cache holds: step 56.6 against 57.6-58.5 us with two sets,
+# bit-identical results)
+MAIN_STORAGE = 3
 FP16_LAUNCH = (256, False, 2)
 BATCH_LAUNCH = (512, False, 0)
 BOX_LAUNCH = (512, True, 0)
@@ -170,7 +175,7 @@ def seeds_section(lbmib, wl, seeds=(1, 2), steps=4000, warmup=200):
     for seed in seeds:
         case = wl.single_128(seed=seed)
         nodes = case["shape"][0] * case["shape"][1] * case["shape"][2]
-        lat = lbmib.from_workload(case)
+        lat = lbmib.from_workload(case, storage=MAIN_STORAGE)
         lat.set_stream_collide_launch(*MAIN_LAUNCH)
         lat.step(warmup)
         lat.sync()
@@ -266,7 +271,8 @@ def paper_box_section(lbmib, wl, steps=500, warmup=50):
 
 def kernels_section(lbmib):
     """Full-grid stream-collide launches alone (serial launch mode, no
-    swimmer), FP32 and FP16-shifted storage, at 128^3 (populations of the
+    swimmer), FP32 (two sets, and one set in place) and FP16-shifted
+    storage, at 128^3 (populations of the
     order of the 256 MB last-level cache, which serves part of the traffic)
     and at 256^3 (2.55 GB FP32, 1.27 GB FP16: HBM only): mean launch
     duration from HIP events stamped by the dispatch packets, algorithmic
@@ -277,7 +283,9 @@ def kernels_section(lbmib):
     the source term is skipped)."""
     out = {}
     for name, edge, storage in (("fp32_128", 128, lbmib.FP32_SHIFTED), ("fp16_128", 128, lbmib.FP16_SHIFTED),
-                                ("fp32_256", 256, lbmib.FP32_SHIFTED), ("fp16_256", 256, lbmib.FP16_SHIFTED)):
+                                ("fp32_256", 256, lbmib.FP32_SHIFTED), ("fp16_256", 256, lbmib.FP16_SHIFTED),
+                                ("fp32inplace_128", 128, lbmib.FP32_INPLACE),
+                                ("fp32inplace_256", 256, lbmib.FP32_INPLACE)):
         lat = lbmib.Lattice((edge, edge, edge), 0.8, storage=storage, width=4, fp16_scale=2.0 ** 20)
         lat.set_body_force((1e-6, 0.0, 0.0))
         lat.set_stream_collide_launch(*KERNEL_LAUNCH)
@@ -416,7 +424,7 @@ def main():
     case = wl.single_128(seed=0)
     nodes = case["shape"][0] * case["shape"][1] * case["shape"][2]
     stream = torch.cuda.Stream()
-    lat = lbmib.from_workload(case, stream=stream)
+    lat = lbmib.from_workload(case, storage=MAIN_STORAGE, stream=stream)
     lat.set_stream_collide_launch(*MAIN_LAUNCH)
 
     lat.step(args.warmup)
@@ -464,13 +472,13 @@ def main():
         "config": {"workload": "single swimmer 128^3 (D3Q19 BGK Guo, tau 0.8, 4-point IBM, "
                                "3 beads r=4 x 1280 triangles, spacing 16, A=5e-4, T=2000)",
                    "grid": list(case["shape"]), "markers": lat.n_markers, "seed": 0,
-                   "storage": "fp32 shifted",
+                   "storage": "fp32 shifted, one set in place",
                    "launch": {"block": MAIN_LAUNCH[0], "xcd_remap": int(MAIN_LAUNCH[1]),
                               "resident": MAIN_LAUNCH[2]}},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
                      "traffic_bytes_per_launch": tbytes,
-                     "kernel": "k_stream_collide<fp32,256,all> (full grid, 19 loads + 19 stores per node)",
+                     "kernel": "k_stream_collide<fp32 in place,256,all> (full grid, 19 loads + 19 stores per node)",
                      "avg_kernel_ms": round(avg_ms, 5), "launches_timed": launches,
                      "bytes_per_launch": lat.bytes_per_step,
                      "copy_probe_gbs": round(copy_gbs, 1),

@@ -59,12 +59,23 @@ extern "C" {
  * physical velocity is rho u = sum f c + F/2 (Sec. 2.1). */
 typedef enum { LBM_GUO = 0, LBM_SHAN_CHEN = 1 } lbm_forcing;
 
-/* Population storage on the device; arithmetic is FP32 in all three.  The
+/* Population storage on the device; arithmetic is FP32 in all four.  The
  * shifted forms store the deviation g = f - w from the rest state;
  * FP16_SHIFTED stores g * scale rounded to nearest-even half precision.
  * FP32_PLAIN stores f itself, rounded at the scale of the weights (~1/3), a
- * reference that shows the precision the shift recovers. */
-typedef enum { LBM_FP32_SHIFTED = 0, LBM_FP16_SHIFTED = 1, LBM_FP32_PLAIN = 2 } lbm_storage;
+ * reference that shows the precision the shift recovers.  FP32_INPLACE
+ * stores the FP32 deviations in ONE population set updated in place (the
+ * AA access pattern of Bailey et al., ICPP 2009: even steps read a node's
+ * own slots and write them back reversed, odd steps read from and write to
+ * the neighbours' slots), half the memory of the two-set pull scheme and
+ * the same streaming and collision bit for bit; one set must stay below
+ * 4 GiB (LBM_EINVAL otherwise).  Not for lbm_adjoint. */
+typedef enum {
+  LBM_FP32_SHIFTED = 0,
+  LBM_FP16_SHIFTED = 1,
+  LBM_FP32_PLAIN = 2,
+  LBM_FP32_INPLACE = 3
+} lbm_storage;
 
 /* ---- descriptors ---------------------------------------------------------- */
 typedef struct {
@@ -235,7 +246,8 @@ int lbm_batch_create(const lbm_box_desc* boxes, int32_t nboxes, const lbm_opts* 
 
 /* Bytes of caller field memory (lbm_opts.field_memory) that a handle over
  * these boxes with this storage (lbm_storage) needs: two population sets
- * (19 values per node, 4 bytes each, 2 with FP16_SHIFTED) plus 3 float32 of
+ * (one with FP32_INPLACE; 19 values per node, 4 bytes each, 2 with
+ * FP16_SHIFTED) plus 3 float32 of
  * body force and 3 of velocity per node, each part padded to the population
  * blocks of 256 nodes.  Host-only; no device is touched.  Errors: LBM_EINVAL
  * (boxes that lbm_batch_create would reject, unknown storage, NULL bytes). */
@@ -309,9 +321,9 @@ typedef struct {
  * per checkpoint; two segment buffers (the recompute of one segment runs
  * beside the reverse sweep of the next) of 28 bytes per node per segment
  * step ((rho, u) and the force density); six population sets.  The adjoint arithmetic is FP32 on the grid and FP64 on the markers
- * and parameter sums.  Single-box handles with FP32 storage; Guo or
+ * and parameter sums.  Single-box handles with FP32_SHIFTED storage; Guo or
  * Shan-Chen forcing (Sec. 2.1, Eq. sc).  Errors: LBM_EINVAL (bad descriptor,
- * batch, FP16 storage), LBM_ENOMEM, LBM_EDEVICE, LBM_EOVERFLOW. */
+ * batch, any other storage), LBM_ENOMEM, LBM_EDEVICE, LBM_EOVERFLOW. */
 int lbm_adjoint(lbm_handle* h, const lbm_adjoint_desc* desc, double* J, double grad[4]);
 
 /* ---- checkpoint ---------------------------------------------------------------- */
@@ -335,13 +347,13 @@ int lbm_kernel_time(lbm_handle* h, double* ms, int64_t* launches);
  * the launch that runs concurrently with the immersed-boundary kernels
  * persistent with that many workgroups per compute unit (0: one workgroup
  * per block; -1: no concurrency, the immersed-boundary kernels then one
- * full-grid launch).  With FP32 storage the persistent workgroups of each XCD
- * claim that XCD's blocks one at a time from a device counter; with FP16
- * storage they walk them in a fixed order.  An XCD's blocks are one
- * contiguous range when remapped, every eighth block otherwise.  Results are
- * bitwise identical for every shape.  Defaults (the fastest measured on
- * MI355X): one box with FP32 storage 512 / no remap / 1; FP16 storage
- * 256 / no remap / 2; batches 512 / remap / 0.
+ * full-grid launch).  With FP32 storage (either form) the persistent
+ * workgroups of each XCD claim that XCD's blocks one at a time from a device
+ * counter; with FP16 storage they walk them in a fixed order.  An XCD's
+ * blocks are one contiguous range when remapped, every eighth block
+ * otherwise.  Results are bitwise identical for every shape.  Defaults (the
+ * fastest measured on MI355X): one box with FP32 storage 512 / no remap / 1;
+ * FP16 storage 256 / no remap / 2; batches 512 / no remap / 0.
  * Errors: LBM_EINVAL. */
 int lbm_set_stream_collide_launch(lbm_handle* h, int block, int xcd_remap, int resident);
 /* Algorithmic bytes one stream-collide launch moves (19 populations read and

@@ -91,7 +91,7 @@ static int valid_box(const abi_box* b) {
 }
 
 static int valid_opts(const abi_opts* o) {
-  if (o->storage < 0 || o->storage > 2) return 0;
+  if (o->storage < 0 || o->storage > 3) return 0;
   if (o->delta_width < 2 || o->delta_width > 4) return 0;
   if (o->fp16_scale != 0.0f) {
     int e;

@@ -80,7 +80,15 @@ __host__ __device__ inline int64_t pop_index(int q, int64_t node) {
 }
 
 enum Forcing { kGuo = 0, kShanChen = 1 };
-enum Storage { kFp32 = 0, kFp16 = 1, kFp32Plain = 2 };
+enum Storage { kFp32 = 0, kFp16 = 1, kFp32Plain = 2, kFp32InPlace = 3 };
+
+// D3Q19 velocities c_q in the population order of the interface (0 rest,
+// 1..6 faces, 7..18 edges, opposite directions adjacent), for host code.
+constexpr int kLatticeC[kQ][3] = {{0, 0, 0},  {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},   {0, -1, 0},
+                                  {0, 0, 1},  {0, 0, -1}, {1, 1, 0},  {-1, -1, 0}, {1, -1, 0},
+                                  {-1, 1, 0}, {1, 0, 1},  {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
+                                  {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+__host__ __device__ constexpr int opposite(int q) { return q == 0 ? 0 : ((q & 1) ? q + 1 : q - 1); }
 enum ScLaunch { kLaunchAll = 0, kLaunchBulk = 1, kLaunchActive = 2 };
 
 // Division of unsigned 32-bit numbers by an invariant d >= 1 through a

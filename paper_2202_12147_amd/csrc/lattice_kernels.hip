@@ -89,6 +89,11 @@ struct PopIO<kFp32Plain> {
   __device__ static inline void st_wt(float* p, int q, float v, float) { stream_store(p, v + weight(q)); }
 };
 
+// In-place FP32 deviations: the element type and decoding of kFp32; its loads
+// and stores are the buffer forms of sc_node_inplace.
+template <>
+struct PopIO<kFp32InPlace> : PopIO<kFp32> {};
+
 // Offsets (in nodes, periodic wrap folded in) of the six face neighbours.
 struct Nbr {
   int xm, xp, ym, yp, zm, zp;
@@ -348,6 +353,154 @@ __device__ inline void sc_node(const Dev& d, const Box& B, int x, int y, int z, 
   }
 }
 
+// ---- in-place storage (one population set) ------------------------------------
+// The AA access pattern (Bailey, Myre, Walsh, Lilja and Lerner, "Accelerating
+// lattice Boltzmann fluid flow simulations using graphics processors", ICPP
+// 2009): one set of deviations, updated in place.  With the state after an
+// odd number of steps (and the initial state) holding f*_q(x) in slot q of
+// node x + c_q, an even step n reads the incoming f_q(x) from its own slot q
+// and writes f*_q(x) back to slot opposite(q) of the same node; after it,
+// slot opposite(q) of node x holds f*_q(x), so an odd step reads f_q(x) =
+// f*_q(x - c_q) from slot opposite(q) of node x - c_q and writes f*_q(x) to
+// slot q of node x + c_q, which restores the first arrangement.  Every node
+// reads and writes the same 19 slots and no other node touches them in that
+// step, so the launches of one step (bulk and near blocks) may run
+// concurrently, as with two sets.  The moments, forcing and collision are
+// those of sc_node, so the results equal the two-set storage bit for bit.
+// Loads and stores go through a buffer resource bounded by the set's size.
+
+// Node offsets of the upstream neighbours x - c_q, periodic wrap folded in.
+__device__ inline void upstream_offsets(const Nbr& o, int* off) {
+  const int t[kQ] = {0,
+                     o.xm, o.xp, o.ym, o.yp, o.zm, o.zp,
+                     o.xm + o.ym, o.xp + o.yp, o.xm + o.yp, o.xp + o.ym,
+                     o.xm + o.zm, o.xp + o.zp, o.xm + o.zp, o.xp + o.zm,
+                     o.ym + o.zm, o.yp + o.zp, o.ym + o.zp, o.yp + o.zm};
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) off[q] = t[q];
+}
+
+// Byte offset of population 0 of node byte offset M = m * 4 in the block layout
+// (m + 4608 (m >> 8) elements, see pull).
+__device__ inline uint32_t inplace_node_bytes(uint32_t M) {
+  return __umul24(M >> 10, (uint32_t)((kQ - 1) * kPopBlock * 4)) + M;
+}
+
+__device__ inline __amdgpu_buffer_rsrc_t inplace_rsrc(const Dev& d) {
+  return __builtin_amdgcn_make_buffer_rsrc(d.pop[0], (short)0, (int)(uint32_t)(kQ * d.pstride * 4), kBufferWord3);
+}
+
+// Slot q of the node at byte offset b (from inplace_node_bytes), as float.
+__device__ inline float inplace_load(__amdgpu_buffer_rsrc_t rs, uint32_t b, int q) {
+  const uint32_t c = (uint32_t)q * kPopBlock * 4u;
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, b + (c & 4095u), c & ~4095u, 0));
+}
+
+// Stores written through (system-coherent, the sc0 sc1 bits) while the set
+// is of the order of the last-level cache, non-temporal above.
+template <int AUX>
+__device__ inline void inplace_store(__amdgpu_buffer_rsrc_t rs, uint32_t b, int q, float v) {
+  const uint32_t c = (uint32_t)q * kPopBlock * 4u;
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), rs, b + (c & 4095u), c & ~4095u, AUX);
+}
+constexpr int kAuxWriteThrough = 17;  // sc0 | sc1
+constexpr int kAuxNonTemporal = 2;    // nt
+
+// The state after `steps` steps, f*_q(x) of node x (byte offset M), into g.
+__device__ inline void inplace_post(__amdgpu_buffer_rsrc_t rs, uint32_t M, const int* off, int64_t steps, float* g) {
+  if (steps & 1) {
+    const uint32_t b = inplace_node_bytes(M);
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) g[q] = inplace_load(rs, b, opposite(q));
+  } else {
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) g[q] = inplace_load(rs, inplace_node_bytes(M + (uint32_t)off[opposite(q)] * 4u), q);
+  }
+}
+
+template <int AUX>
+__device__ inline void inplace_push(__amdgpu_buffer_rsrc_t rs, uint32_t M, const int* off, bool odd, const float* g) {
+  if (!odd) {
+    const uint32_t b = inplace_node_bytes(M);
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) inplace_store<AUX>(rs, b, opposite(q), g[q]);
+  } else {
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) inplace_store<AUX>(rs, inplace_node_bytes(M + (uint32_t)off[opposite(q)] * 4u), q, g[q]);
+  }
+}
+
+// SERIAL: a full-grid launch with no concurrent kernels, whose odd-step
+// stores go plain (the L2 merges the partial lines of the neighbours'
+// scattered runs: 128^3 FP32 launch 48.1 against 50.2 us written through);
+// beside the immersed-boundary kernels they stay written through (plain:
+// step 58.9 against 56.8 us, the L2 taken from the concurrent kernels).
+template <bool SERIAL>
+__device__ inline void sc_node_inplace(const Dev& d, const Box& B, int x, int y, int z, int64_t base, int64_t n,
+                                       bool forced, bool avg) {
+  const Nbr o = neighbours(x, y, z, B.nx, B.ny, B.nz);
+  int off[kQ];
+  upstream_offsets(o, off);
+  const __amdgpu_buffer_rsrc_t rs = inplace_rsrc(d);
+  const int64_t ps = d.pstride;
+  const uint32_t M = (uint32_t)base * 4u;
+  const bool odd = (n & 1) != 0;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  if (avg) {
+    a0 = d.uavg[base];
+    a1 = d.uavg[ps + base];
+    a2 = d.uavg[2 * ps + base];
+  }
+  float g[kQ];
+  if (!odd) {
+    const uint32_t b = inplace_node_bytes(M);
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) g[q] = inplace_load(rs, b, q);
+  } else {
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) g[q] = inplace_load(rs, inplace_node_bytes(M + (uint32_t)off[q] * 4u), opposite(q));
+  }
+  const Moments m = moments(g);
+  float Fx = B.gx, Fy = B.gy, Fz = B.gz;
+  if (forced) {
+    Fx += d.F[base];
+    Fy += d.F[ps + base];
+    Fz += d.F[2 * ps + base];
+  }
+  const float ir = inv_density(m.rho);
+  const float ux = (m.jx + 0.5f * Fx) * ir;
+  const float uy = (m.jy + 0.5f * Fy) * ir;
+  const float uz = (m.jz + 0.5f * Fz) * ir;
+  if (forced) {
+    d.u[base] = ux;
+    d.u[ps + base] = uy;
+    d.u[2 * ps + base] = uz;
+  }
+  float ex = ux, ey = uy, ez = uz, src_a = 1.0f - 0.5f * B.omega;
+  if (B.forcing == kShanChen) {
+    ex = (m.jx + B.tau * Fx) * ir;
+    ey = (m.jy + B.tau * Fy) * ir;
+    ez = (m.jz + B.tau * Fz) * ir;
+    src_a = 0.0f;
+  }
+  if (src_a != 0.0f && (Fx != 0.0f || Fy != 0.0f || Fz != 0.0f))
+    collide_all<true>(g, m, B.omega, ex, ey, ez, src_a, ux, uy, uz, Fx, Fy, Fz);
+  else
+    collide_all<false>(g, m, B.omega, ex, ey, ez, src_a, ux, uy, uz, Fx, Fy, Fz);
+  if (!d.small_pops)
+    inplace_push<kAuxNonTemporal>(rs, M, off, odd, g);
+  else if (SERIAL && odd)
+    inplace_push<0>(rs, M, off, true, g);
+  else
+    inplace_push<kAuxWriteThrough>(rs, M, off, odd, g);
+  if (avg) {
+    double* __restrict__ acc = d.uavg;
+    acc[base] = a0 + (double)ux;
+    acc[ps + base] = a1 + (double)uy;
+    acc[2 * ps + base] = a2 + (double)uz;
+  }
+}
+
 // Whether step n adds to the time-average sums (uniform over a launch).
 __device__ inline bool avg_sampled(const Dev& d, int64_t n) {
   return d.uavg != nullptr && n >= d.avg_t0 && (n - d.avg_t0) % d.avg_every == 0;
@@ -364,7 +517,7 @@ __device__ inline bool avg_sampled(const Dev& d, int64_t n) {
 //             tile is active.
 constexpr int kScAll = kLaunchAll, kScBulk = kLaunchBulk, kScActive = kLaunchActive;
 
-template <int ST, int BS, bool MOM = false, bool NTLD = true>
+template <int ST, int BS, bool MOM = false, bool NTLD = true, bool SERIAL = false>
 __device__ inline void sc_block(const Dev& d, int blk, int64_t n, bool bulk, bool avg) {
   const int b = d.nboxes == 1 ? 0 : d.sc_block_box[blk];
   const Box B = d.boxes[b];
@@ -383,11 +536,15 @@ __device__ inline void sc_block(const Dev& d, int blk, int64_t n, bool bulk, boo
     forced = d.stamp[tile] == (int)n;
   }
   // the two addressing forms as separate code (a population set below 4 GiB
-  // takes 32-bit offsets)
-  if (d.pops32)
+  // takes 32-bit offsets; the in-place set always does)
+  if constexpr (ST == kFp32InPlace) {
+    static_assert(!MOM, "the in-place storage does not record moments");
+    sc_node_inplace<SERIAL>(d, B, x, y, z, B.node0 + id, n, forced, avg);
+  } else if (d.pops32) {
     sc_node<ST, MOM, NTLD, true>(d, B, x, y, z, B.node0 + id, n, forced, avg);
-  else
+  } else {
     sc_node<ST, MOM, NTLD, false>(d, B, x, y, z, B.node0 + id, n, forced, avg);
+  }
 }
 
 // AVG: the variant launched while a time average of u runs (the sampling
@@ -455,7 +612,7 @@ __global__ __launch_bounds__(BS) void k_stream_collide(Dev d, int remap, int nbl
     }
   } else {
     const int blk = logical_block(remap, nblocks);
-    if (blk < nblocks) sc_block<ST, BS, false, NTLD>(d, blk, n, false, avg);
+    if (blk < nblocks) sc_block<ST, BS, false, NTLD, true>(d, blk, n, false, avg);
   }
 }
 
@@ -555,11 +712,22 @@ __global__ __launch_bounds__(kScBlock) void k_velocity(Dev d, float* __restrict_
   const int y = yz % ny;
   const int z = yz / ny;
   const Nbr o = neighbours(x, y, z, nx, ny, nz);
-  const T* src = static_cast<const T*>(d.pop[n & 1]);
   const int64_t ps = d.pstride;
   const int64_t base = B.node0 + id;
   float g[kQ];
-  pull<ST>(src, base, o, d.fp16_inv, g);
+  // the incoming populations of step n (two sets: still in the set step n
+  // read), or, in place, the post-collision ones, whose momentum is j + F
+  // (the collision adds the force density once, Guo or Shan-Chen)
+  float hf = 0.5f;
+  if constexpr (ST == kFp32InPlace) {
+    int off[kQ];
+    upstream_offsets(o, off);
+    inplace_post(inplace_rsrc(d), (uint32_t)base * 4u, off, c, g);
+    hf = -0.5f;
+  } else {
+    const T* src = static_cast<const T*>(d.pop[n & 1]);
+    pull<ST>(src, base, o, d.fp16_inv, g);
+  }
   const Moments m = moments(g);
   float Fx = B.gx, Fy = B.gy, Fz = B.gz;
   const int tile = B.tile0 + (x / kTile) + B.tx * ((y / kTile) + B.ty * (z / kTile));
@@ -570,9 +738,9 @@ __global__ __launch_bounds__(kScBlock) void k_velocity(Dev d, float* __restrict_
   }
   const float ir = inv_density(m.rho);
   if (uo) {
-    uo[ob] = (m.jx + 0.5f * Fx) * ir;
-    uo[nb + ob] = (m.jy + 0.5f * Fy) * ir;
-    uo[2 * nb + ob] = (m.jz + 0.5f * Fz) * ir;
+    uo[ob] = (m.jx + hf * Fx) * ir;
+    uo[nb + ob] = (m.jy + hf * Fy) * ir;
+    uo[2 * nb + ob] = (m.jz + hf * Fz) * ir;
   }
   if (ro) ro[orho] = m.rho;
 }
@@ -625,8 +793,16 @@ __global__ __launch_bounds__(kScBlock) void k_conserved_partial(Dev d, int box, 
     for (int64_t id = (int64_t)blockIdx.x * kScBlock + threadIdx.x; id < B.n;
          id += (int64_t)gridDim.x * kScBlock) {
       float g[kQ];
+      if constexpr (ST == kFp32InPlace) {
+        // each node's own 19 post-collision values, wherever they are stored
+        const int x = (int)(id % B.nx), yz = (int)(id / B.nx), y = yz % B.ny, z = yz / B.ny;
+        int off[kQ];
+        upstream_offsets(neighbours(x, y, z, B.nx, B.ny, B.nz), off);
+        inplace_post(inplace_rsrc(d), (uint32_t)(B.node0 + id) * 4u, off, c, g);
+      } else {
 #pragma unroll
-      for (int q = 0; q < kQ; ++q) g[q] = IO::ld(src + pop_index(q, B.node0 + id), q, d.fp16_inv);
+        for (int q = 0; q < kQ; ++q) g[q] = IO::ld(src + pop_index(q, B.node0 + id), q, d.fp16_inv);
+      }
       const Moments m = moments(g);
       v[0] += (double)m.drho;
       v[1] += (double)m.jx;
@@ -721,11 +897,14 @@ static void launch_sc_ld(const Dev& d, int mode, int block, int nblocks, int rem
     launch_sc_mode<ST, kScAll, AVG, NTLD>(d, block, nblocks, remap, resident, ncu, s, ev0, ev1);
 }
 
-// FP16 pulls are plain loads in either regime (one instance)
+// FP16 pulls are plain loads in either regime, and the in-place set has one
+// load form (one instance each)
 template <int ST, bool AVG>
 static void launch_sc_avg(const Dev& d, int mode, int block, int nblocks, int remap, int resident,
                           int ncu, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
-  if (d.small_pops || ST == kFp16)
+  if constexpr (ST == kFp16 || ST == kFp32InPlace)
+    launch_sc_ld<ST, AVG, true>(d, mode, block, nblocks, remap, resident, ncu, s, ev0, ev1);
+  else if (d.small_pops)
     launch_sc_ld<ST, AVG, true>(d, mode, block, nblocks, remap, resident, ncu, s, ev0, ev1);
   else
     launch_sc_ld<ST, AVG, false>(d, mode, block, nblocks, remap, resident, ncu, s, ev0, ev1);
@@ -746,6 +925,8 @@ void launch_stream_collide(const Dev& d, int storage, int mode, int block, int n
     launch_sc_st<kFp16>(d, mode, block, nblocks, remap, resident, ncu, s, ev0, ev1);
   else if (storage == kFp32Plain)
     launch_sc_st<kFp32Plain>(d, mode, block, nblocks, remap, resident, ncu, s, ev0, ev1);
+  else if (storage == kFp32InPlace)
+    launch_sc_st<kFp32InPlace>(d, mode, block, nblocks, remap, resident, ncu, s, ev0, ev1);
   else
     launch_sc_st<kFp32>(d, mode, block, nblocks, remap, resident, ncu, s, ev0, ev1);
 }
@@ -769,6 +950,8 @@ void launch_velocity(const Dev& d, int storage, int nblocks, float* u_out, float
     hipLaunchKernelGGL(k_velocity<kFp16>, dim3(nblocks), dim3(kScBlock), 0, s, d, u_out, rho_out);
   else if (storage == kFp32Plain)
     hipLaunchKernelGGL(k_velocity<kFp32Plain>, dim3(nblocks), dim3(kScBlock), 0, s, d, u_out, rho_out);
+  else if (storage == kFp32InPlace)
+    hipLaunchKernelGGL(k_velocity<kFp32InPlace>, dim3(nblocks), dim3(kScBlock), 0, s, d, u_out, rho_out);
   else
     hipLaunchKernelGGL(k_velocity<kFp32>, dim3(nblocks), dim3(kScBlock), 0, s, d, u_out, rho_out);
 }
@@ -783,6 +966,8 @@ void launch_conserved(const Dev& d, int storage, int box, double* partial, int n
     hipLaunchKernelGGL(k_conserved_partial<kFp16>, dim3(nparts), dim3(kScBlock), 0, s, d, box, partial);
   else if (storage == kFp32Plain)
     hipLaunchKernelGGL(k_conserved_partial<kFp32Plain>, dim3(nparts), dim3(kScBlock), 0, s, d, box, partial);
+  else if (storage == kFp32InPlace)
+    hipLaunchKernelGGL(k_conserved_partial<kFp32InPlace>, dim3(nparts), dim3(kScBlock), 0, s, d, box, partial);
   else
     hipLaunchKernelGGL(k_conserved_partial<kFp32>, dim3(nparts), dim3(kScBlock), 0, s, d, box, partial);
   hipLaunchKernelGGL(k_conserved_final, dim3(1), dim3(kScBlock), 0, s, partial, nparts, out, mass0);

@@ -121,12 +121,27 @@ int reserved_tiles(double radius, int width, int n, int T) {
 
 // Host layout of population deviations: box after box, each [19][n_box];
 // device index pop_index(q, node0_b + n) (256-node population blocks).
+// With the in-place storage the current state's f*_q(x) sits in slot q of
+// node x + c_q after an even number of steps (and initially), in slot
+// opposite(q) of node x after an odd number.
 template <class F>
 void for_each_population(const lbm_handle* h, F f) {
+  const bool inplace = h->storage == LBM_FP32_INPLACE, odd = (h->host_step & 1) != 0;
   for (const Box& B : h->boxes) {
     const int64_t hoff = kQ * B.node0;
     for (int q = 0; q < kQ; ++q)
-      for (int64_t n = 0; n < B.n; ++n) f(hoff + q * B.n + n, pop_index(q, B.node0 + n), q);
+      for (int64_t n = 0; n < B.n; ++n) {
+        int64_t di = pop_index(q, B.node0 + n);
+        if (inplace && odd) {
+          di = pop_index(opposite(q), B.node0 + n);
+        } else if (inplace) {
+          const int64_t x = n % B.nx, y = (n / B.nx) % B.ny, z = n / ((int64_t)B.nx * B.ny);
+          const int64_t xs = (x + kLatticeC[q][0] + B.nx) % B.nx, ys = (y + kLatticeC[q][1] + B.ny) % B.ny,
+                        zs = (z + kLatticeC[q][2] + B.nz) % B.nz;
+          di = pop_index(q, B.node0 + xs + B.nx * (ys + B.ny * zs));
+        }
+        f(hoff + q * B.n + n, di, q);
+      }
   }
 }
 
@@ -602,23 +617,30 @@ int check_boxes(const lbm_box_desc* boxes, int nboxes, int64_t* nodes) {
 }
 
 bool valid_storage(int storage) {
-  return storage == LBM_FP32_SHIFTED || storage == LBM_FP16_SHIFTED || storage == LBM_FP32_PLAIN;
+  return storage == LBM_FP32_SHIFTED || storage == LBM_FP16_SHIFTED || storage == LBM_FP32_PLAIN ||
+         storage == LBM_FP32_INPLACE;
 }
 
-// The node fields in one allocation: population sets 0 and 1, then the
-// body-force density and the velocity ([3][pstride] float32 each).  Every
-// part is a multiple of 256 bytes long (pstride is a multiple of the
-// 256-node population block), so each starts 256-byte aligned.
+// Population sets a storage keeps: one updated in place, else two.
+int population_sets(int storage) { return storage == LBM_FP32_INPLACE ? 1 : 2; }
+
+// The node fields in one allocation: the population sets (0 and 1, or the
+// one in-place set), then the body-force density and the velocity
+// ([3][pstride] float32 each).  Every part is a multiple of 256 bytes long
+// (pstride is a multiple of the 256-node population block), so each starts
+// 256-byte aligned.
 struct FieldLayout {
   size_t pop, vec, total;  // bytes of one population set, of F (or u), of all
+  int sets;
 };
 
 FieldLayout field_layout(int64_t nodes, int storage) {
   const int64_t pstride = (nodes + kPopBlock - 1) / kPopBlock * kPopBlock;
   FieldLayout L;
+  L.sets = population_sets(storage);
   L.pop = (size_t)(storage == LBM_FP16_SHIFTED ? 2 : 4) * kQ * (size_t)pstride;
   L.vec = sizeof(float) * 3 * (size_t)pstride;
-  L.total = 2 * L.pop + 2 * L.vec;
+  L.total = L.sets * L.pop + 2 * L.vec;
   return L;
 }
 
@@ -630,6 +652,8 @@ int create_boxes(const lbm_box_desc* boxes, int nboxes, const lbm_opts* opts, lb
   lbm_opts o{LBM_FP32_SHIFTED, 3, 1.0f, 1, nullptr, nullptr, 0};
   if (opts) o = *opts;
   if (!valid_storage(o.storage)) return LBM_EINVAL;
+  // the in-place set is addressed with 32-bit byte offsets
+  if (o.storage == LBM_FP32_INPLACE && field_layout(total, o.storage).pop >= ((size_t)1 << 32)) return LBM_EINVAL;
   if (o.field_memory) {
     if (((uintptr_t)o.field_memory & 255) != 0) return LBM_EINVAL;
     if (o.field_bytes < 0 || (uint64_t)o.field_bytes < field_layout(total, o.storage).total) return LBM_EINVAL;
@@ -727,12 +751,13 @@ int create_boxes(const lbm_box_desc* boxes, int nboxes, const lbm_opts* opts, lb
     const FieldLayout L = field_layout(h->nodes, h->storage);
     char* base = static_cast<char*>(o.field_memory);
     h->pop[0] = base;
-    h->pop[1] = base + L.pop;
-    h->F = reinterpret_cast<float*>(base + 2 * L.pop);
-    h->u = reinterpret_cast<float*>(base + 2 * L.pop + L.vec);
+    h->pop[1] = base + (L.sets - 1) * L.pop;
+    h->F = reinterpret_cast<float*>(base + L.sets * L.pop);
+    h->u = reinterpret_cast<float*>(base + L.sets * L.pop + L.vec);
   } else {
     h->pop[0] = h->alloc<char>(eb * kQ * h->pstride, rc);
-    h->pop[1] = h->alloc<char>(eb * kQ * h->pstride, rc);
+    // the in-place storage names its one set twice
+    h->pop[1] = population_sets(h->storage) == 2 ? h->alloc<char>(eb * kQ * h->pstride, rc) : h->pop[0];
     h->F = h->alloc<float>(3 * h->pstride, rc);
     h->u = h->alloc<float>(3 * h->pstride, rc);
   }
@@ -790,7 +815,7 @@ int create_boxes(const lbm_box_desc* boxes, int nboxes, const lbm_opts* opts, lb
   d.step = h->d_step;
   d.sub = 0;
   d.fp16_scale = h->fp16_scale;
-  d.small_pops = 2 * kQ * h->pstride * (int64_t)element_bytes(h) <= kWriteThroughBytes ? 1 : 0;
+  d.small_pops = population_sets(h->storage) * kQ * h->pstride * (int64_t)element_bytes(h) <= kWriteThroughBytes ? 1 : 0;
   d.pops32 = kQ * h->pstride * (int64_t)element_bytes(h) < ((int64_t)1 << 32) ? 1 : 0;
   d.fp16_inv = 1.0f / h->fp16_scale;
   d.width = h->width;

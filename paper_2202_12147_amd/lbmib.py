@@ -15,7 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbmib.so")
 
 GUO, SHAN_CHEN = 0, 1
-FP32_SHIFTED, FP16_SHIFTED, FP32_PLAIN = 0, 1, 2
+FP32_SHIFTED, FP16_SHIFTED, FP32_PLAIN, FP32_INPLACE = 0, 1, 2, 3
 
 ERRORS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EDEVICE", -4: "LBM_ESTATE",
           -5: "LBM_ENONFINITE", -6: "LBM_EIO", -7: "LBM_EOVERFLOW"}

@@ -80,6 +80,8 @@ def test_field_bytes_and_caller_memory_checks():
     padded = -(-(100 * 20 * 17 + 16 * 16 * 17) // 256) * 256
     assert lbmib.field_bytes(ragged) == padded * (2 * 19 * 4 + 24)
     assert lbmib.field_bytes(ragged, lbmib.FP32_PLAIN) == padded * (2 * 19 * 4 + 24)
+    # the in-place storage keeps one population set
+    assert lbmib.field_bytes([((128, 128, 128), 0.8, 0)], lbmib.FP32_INPLACE) == 128 ** 3 * (19 * 4 + 24)
     assert lib.lbm_field_bytes(one, 1, 9, C.byref(out)) == -1  # storage
     assert lib.lbm_field_bytes(one, 1, 0, None) == -1
     assert lib.lbm_field_bytes(one, 0, 0, C.byref(out)) == -1
@@ -93,6 +95,10 @@ def test_field_bytes_and_caller_memory_checks():
     o = lbmib.Opts(0, 3, 1.0, 1, None, 0x10000, need - 1)  # too small
     assert lib.lbm_create(C.byref(g), 1.0, 0, C.byref(o), C.byref(h)) == -1
     assert lib.lbm_batch_create(one, 1, C.byref(o), C.byref(h)) == -1
+    # one in-place set must stay below 4 GiB (32-bit byte offsets):
+    # 1024 x 512 x 128 nodes x 76 bytes = 5.1 GB
+    o = lbmib.Opts(3, 3, 1.0, 1, None, None, 0)
+    assert lib.lbm_create(C.byref(lbmib.Grid(1024, 512, 128)), 1.0, 0, C.byref(o), C.byref(h)) == -1
     assert h.value is None
 
 
