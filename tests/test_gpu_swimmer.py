@@ -82,12 +82,15 @@ def test_small_case_full_run():
     assert np.abs(c[1:]).max() < 1e-6
 
 
-def test_single_128_parity_200_steps():
+@pytest.mark.parametrize("storage", [lbmib.FP32_SHIFTED, bench.MAIN_STORAGE])
+def test_single_128_parity_200_steps(storage):
     # the 128^3, 4-point, 1280-triangle workload at full size, in the launch
     # configuration the benchmark times (its 32-step graph replayed six
-    # times, then the 8-step graph): the whole field element by element
+    # times, then the 8-step graph; two population sets and the benchmark's
+    # one set in place): the whole field element by element
     case = wl.single_128(seed=0)
-    o, lat = _run_pair(case, 200, launch=bench.MAIN_LAUNCH)
+    print("128^3 200 steps, storage", storage, flush=True)
+    o, lat = _run_pair(case, 200, storage=storage, launch=bench.MAIN_LAUNCH)
     u, uo = lat.velocity(), o.velocity()
     du, dmax = rel_l2(u, uo), max_rel(u, uo)
     dr = np.abs(lat.markers() - o.markers()).max()
@@ -99,13 +102,14 @@ def test_single_128_parity_200_steps():
 
 def test_single_128_first_period_trajectory():
     """Swimmer centre X(n) over the first actuation period (2000 steps) of the
-    128^3 workload in the benchmark's launch configuration, against the FP64
+    128^3 workload in the benchmark's launch configuration and storage (one
+    population set in place), against the FP64
     oracle's trajectory stored by tests/golden/make_trajectory_golden.py,
     read after every 32-step graph: X within POS_PER_STEP per step, the
     displacement X(n) - X(0) within 1e-3 of the oracle's largest one."""
     ref = np.loadtxt(os.path.join(GOLDEN, "single128_x_2000.txt"))
     case = wl.single_128(seed=0)
-    lat = lbmib.from_workload(case)
+    lat = lbmib.from_workload(case, storage=bench.MAIN_STORAGE)
     lat.set_stream_collide_launch(*bench.MAIN_LAUNCH)
     X0 = lat.swimmer_centres()[0]
     np.testing.assert_allclose(X0, ref[0, 1:], rtol=0, atol=1e-12)
