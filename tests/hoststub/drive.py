@@ -98,8 +98,8 @@ def single(case, tmp, storage=lbmib.FP32_SHIFTED, scale=1.0, graphs=True):
     lat.close()
 
 
-def batch(ens, tmp, graphs=True):
-    b = lbmib.batch_from_ensemble(ens, use_graphs=graphs)
+def batch(ens, tmp, graphs=True, storage=lbmib.FP32_SHIFTED):
+    b = lbmib.batch_from_ensemble(ens, storage=storage, use_graphs=graphs)
     observables(b, batch=True)
     step_pattern(b)
     averages(b, batch=True)
@@ -109,6 +109,29 @@ def batch(ens, tmp, graphs=True):
     b.load(path)
     observables(b, batch=True)
     b.close()
+
+
+def caller_field_memory(case, storage):
+    """A handle whose node fields live in a caller buffer (here host memory,
+    which the stand-in's device memory is): every byte the library writes must
+    stay inside the lbm_field_bytes it asked for."""
+    lib = lbmib._lib
+    need = lbmib.field_bytes([(case["shape"], case["tau"], case["forcing"])], storage)
+    raw = np.zeros(need + 512, np.uint8)
+    start = (-raw.ctypes.data) % 256
+    buf = raw[start:start + need]  # exactly the asked-for bytes, 256-byte aligned
+    o = lbmib.Opts(int(storage), int(case["width"]), 1.0, 1, None, buf.ctypes.data, need)
+    h = C.c_void_p()
+    assert lib.lbm_create(C.byref(lbmib.Grid(*case["shape"])), float(case["tau"]), int(case["forcing"]), C.byref(o),
+                          C.byref(h)) == 0
+    lat = object.__new__(lbmib.Lattice)
+    lat.lib, lat.h, lat.shape, lat.storage, lat.field_tensor = lib, h, tuple(case["shape"]), storage, None
+    for sw in case.get("swimmers", []):
+        lat.add_swimmer(sw)
+    step_pattern(lat)
+    observables(lat)
+    lat.close()
+    assert raw[:start].max(initial=0) == 0 and raw[start + need:].max(initial=0) == 0
 
 
 def tuner_disabled(lat, tmp):
@@ -178,6 +201,11 @@ def main():
     single(small, tmp)
     single(small, tmp, storage=lbmib.FP16_SHIFTED, scale=2.0 ** 27)
     single(small, tmp, storage=lbmib.FP32_PLAIN)
+    single(small, tmp, storage=lbmib.FP32_INPLACE)
+    single(dict(small, shape=(20, 17, 19), swimmers=[]), tmp, storage=lbmib.FP32_INPLACE)
+    caller_field_memory(small, lbmib.FP32_SHIFTED)
+    caller_field_memory(small, lbmib.FP32_INPLACE)
+    caller_field_memory(dict(small, shape=(20, 17, 19), swimmers=[]), lbmib.FP16_SHIFTED)
     single(dict(small, width=2), tmp, graphs=False)
     seams = dict(small, shape=(33, 30, 29))
     seams["swimmers"] = [wl.swimmer((31.5, 0.6, 28.2), 10.0, A=1e-3, T=500.0)]
@@ -187,6 +215,7 @@ def main():
     tuner_sequence(tmp)
     batch(wl.ensemble(seed=2, nboxes=3), tmp)
     batch(wl.ensemble(seed=7, nboxes=5), tmp, graphs=False)
+    batch(wl.ensemble(seed=7, nboxes=3), tmp, storage=lbmib.FP32_INPLACE)
     ragged = dict(boxes=[dict(wl.small_case(), shape=(20, 17, 19), swimmers=[]),
                          dict(wl.small_case(), shape=(33, 30, 29)),
                          dict(wl.small_case(), shape=(24, 20, 17), forcing=wl.SHAN_CHEN, swimmers=[])])
