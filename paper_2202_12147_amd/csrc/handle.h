@@ -14,11 +14,11 @@
 namespace lbmib {
 
 constexpr int kGraphChunk = 32;  // steps per captured graph
-// Step graphs of 1, 2, 4, ..., kGraphChunk steps: a call of n steps replays
-// the chunk graph n / kGraphChunk times and the rest by its binary digits, so
-// every graph keeps the two-stream overlap of its steps.
-constexpr int kGraphLevels = 6;
-static_assert((1 << (kGraphLevels - 1)) == kGraphChunk, "graph levels end at the chunk");
+// Step graphs of every count 1..kGraphChunk: a call of n steps replays the
+// graph of n mod kGraphChunk steps once, then the chunk graph n / kGraphChunk
+// times, so a call of up to 32 steps is one graph (one fork and join of the
+// two streams; a 20-step call 59.3-60.1 against 61.5-61.8 us per step with
+// the binary split into graphs of 4 and 16 steps).
 
 template <class T>
 T* dev_alloc(size_t n, int& rc) {
@@ -108,7 +108,7 @@ struct lbm_handle {
 
   Dev dev{};
   lbmib::rt::AdjWork* adj = nullptr;  // adjoint buffers, kept between calls
-  hipGraphExec_t g_steps[lbmib::kGraphLevels] = {};  // 1 << l steps each
+  hipGraphExec_t g_steps[lbmib::kGraphChunk + 1] = {};  // g_steps[c]: c steps
 
   bool timing = false;
   double timed_ms = 0;
