@@ -452,9 +452,11 @@ class Lattice:
 # Stream-collide launch shapes (block, xcd_remap, resident) the tuner tries:
 # workgroups of 128 / 256 / 512 nodes, block order round robin over the XCDs
 # or one contiguous range per XCD, one workgroup per block or 1-4 persistent
-# workgroups per CU.
+# workgroups per CU beside the immersed-boundary kernels, or (resident -1)
+# the serial order: those kernels, then one full-grid launch.
 LAUNCH_CANDIDATES = ((512, True, 0), (512, False, 0), (256, True, 0), (256, False, 0), (128, True, 0),
-                     (512, False, 1), (512, True, 1), (512, False, 2), (256, False, 2), (256, False, 4))
+                     (512, False, 1), (512, True, 1), (512, False, 2), (256, False, 2), (256, False, 4),
+                     (512, False, -1), (256, False, -1))
 
 
 def tune_launch(make, candidates=LAUNCH_CANDIDATES, steps=200, warmup=50, rounds=2):
