@@ -3,7 +3,8 @@ hip_stub.cpp, through the call sequences of the GPU tests and the benchmark
 (argument marshalling, handle lifetimes, launch-shape and graph changes, the
 tuner, the adjoint's workspaces and graph caches, checkpoints, averages,
 batches).  Run by tests/test_host_asan.py under AddressSanitizer; the
-results are meaningless (no kernel runs), only memory errors matter.
+results are meaningless (no kernel runs), only memory errors matter, except
+for the host's own population index map, which inplace_mapping checks.
 
     python tests/hoststub/drive.py <path of the stub-built library> <scratch dir>
 """
@@ -134,6 +135,26 @@ def caller_field_memory(case, storage):
     assert raw[:start].max(initial=0) == 0 and raw[start + need:].max(initial=0) == 0
 
 
+def inplace_mapping():
+    """The host's map between the interface's population layout and the
+    in-place set: with no kernel running (the stand-in's launches do
+    nothing), what set_populations stores reads back unchanged at step 0,
+    and after one (empty) step, whose parity moves every value to the other
+    arrangement, reads back as a permutation of the same values."""
+    shape = (20, 17, 19)
+    lat = lbmib.Lattice(shape, 0.9, storage=lbmib.FP32_INPLACE)
+    dev = np.random.default_rng(3).standard_normal(19 * 20 * 17 * 19) * 1e-3
+    lat.set_populations(dev)
+    stored = dev.astype(np.float32).astype(np.float64)
+    assert np.array_equal(lat.populations().ravel(), stored)
+    lat.step(1)
+    lat.sync()
+    got = lat.populations().ravel()
+    assert not np.array_equal(got, stored)
+    assert np.array_equal(np.sort(got), np.sort(stored))
+    lat.close()
+
+
 def tuner_disabled(lat, tmp):
     """The tuner returns LBM_ESTATE and an empty report."""
     for cache in (None, os.path.join(tmp, "tune.txt")):
@@ -203,6 +224,7 @@ def main():
     single(small, tmp, storage=lbmib.FP32_PLAIN)
     single(small, tmp, storage=lbmib.FP32_INPLACE)
     single(dict(small, shape=(20, 17, 19), swimmers=[]), tmp, storage=lbmib.FP32_INPLACE)
+    inplace_mapping()
     caller_field_memory(small, lbmib.FP32_SHIFTED)
     caller_field_memory(small, lbmib.FP32_INPLACE)
     caller_field_memory(dict(small, shape=(20, 17, 19), swimmers=[]), lbmib.FP16_SHIFTED)
